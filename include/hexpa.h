@@ -1,0 +1,273 @@
+/*
+ * hexpa -- matrix-free high-order hexahedral finite-element operators for
+ * MI355X (gfx950), behind a plain C ABI.
+ *
+ * What is computed (Kolev et al., "Efficient Exascale Discretizations:
+ * High-Order Finite Element Methods", 2021):
+ *   - Benchmarks section: the bake-off problems BP1-BP6, CG solves of
+ *     (alpha A + beta B) u = B f with homogeneous Dirichlet conditions, where
+ *     A_ij = int grad phi_i . grad phi_j and B_ij = int phi_i phi_j on
+ *     isoparametric Q_p bricks; Gauss rule with q = p+2 points for BP1-BP4,
+ *     integration on the GLL nodes (q = p+1) for BP5-BP6; scalar (m = 1) and
+ *     vector (m = 3) problems.
+ *   - libCEED section, operator decomposition: the action on an L-vector is
+ *     G^T B^T D B G -- element restriction G, basis evaluation B, pointwise
+ *     quadrature-point operator D, then the transposes -- and the matrix is
+ *     never formed. Each apply below is one fused pass of that product.
+ *   - Miniapps section (Nekbone): CG with a diagonal (Jacobi) preconditioner.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns hx_status: HX_OK (0) or a negative code. No
+ *     function aborts or throws across the ABI; hx_last_error() returns a
+ *     thread-local message describing the last failure on this thread.
+ *   - "host" pointers are ordinary CPU memory, read during the call only.
+ *     "device" pointers are GPU memory on the current HIP device, owned by the
+ *     caller, contiguous, 16-byte aligned, not aliased between input and
+ *     output.
+ *   - hx_stream is a hipStream_t (NULL = the default stream). Work is enqueued
+ *     on it in order; entry points marked "asynchronous" return before the GPU
+ *     finishes.
+ *   - Handles are created and destroyed by the caller. A handle owns its
+ *     device buffers (geometric factors, index arrays, work vectors) and frees
+ *     them in its destroy call. An operator keeps a reference to its mesh and
+ *     basis; destroy the operator first.
+ *   - L-vectors hold one value per mesh node and component; for ncomp = 3 the
+ *     components are interleaved: entry 3*node + c.
+ *   - Calls on one handle from several host threads at once are not
+ *     supported. Two operators may be used concurrently on different streams.
+ */
+#ifndef HEXPA_H
+#define HEXPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hx_status;
+enum {
+  HX_OK = 0,
+  HX_EINVAL = -1,       /* a null pointer, a size or an enum out of range          */
+  HX_ERANGE = -2,       /* an index in elem_nodes outside [0, nnodes)              */
+  HX_EUNSUPPORTED = -3, /* a valid combination this library does not implement     */
+  HX_EGEOM = -4,        /* a non-positive Jacobian determinant found at setup      */
+  HX_ENOCONV = -5,      /* a solve stopped at maxit; the info struct is filled     */
+  HX_EBREAKDOWN = -6,   /* p'Ap <= 0, r'z <= 0 or a non-finite scalar in a solve   */
+  HX_EHIP = -7,         /* a HIP runtime error; its text is in hx_last_error()     */
+  HX_ENOMEM = -8        /* a device or host allocation failed                      */
+};
+
+enum { HX_GAUSS = 0, HX_GLL = 1 };          /* quadrature rule families               */
+enum { HX_MASS = 0, HX_DIFFUSION = 1 };      /* B and A of the bake-off problems       */
+enum { HX_FP64 = 0, HX_FP32 = 1, HX_BF16 = 2 };
+
+typedef struct hx_mesh_s *hx_mesh;
+typedef struct hx_basis_s *hx_basis;
+typedef struct hx_op_s *hx_op;
+typedef void *hx_stream; /* hipStream_t */
+
+/* Text of the last error on the calling thread ("" if none). Never NULL. */
+const char *hx_last_error(void);
+
+/* Library version string. */
+const char *hx_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Meshes                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Coordinates of the Q_p nodes of a mesh of trilinear bricks.
+ * Benchmarks section: elements are mapped from the reference cube [-1,1]^3 by
+ * x^e(r); for a trilinear brick that map is the Q_1 interpolant of its 8
+ * vertices, evaluated here at the (p+1)^3 Gauss-Lobatto-Legendre nodes.
+ *   p           polynomial degree, 1..8
+ *   elem_verts  host, nelem*8, vertex ids; vertex a+2b+4c sits at reference
+ *               corner (2a-1, 2b-1, 2c-1)
+ *   verts       host, nverts*3 FP64 coordinates
+ *   elem_nodes  host, nelem*(p+1)^3 node ids, element-local order i fastest
+ *   node_xyz    host output, nnodes*3 FP64; nodes listed by no element are 0
+ * Errors: HX_EINVAL (null, sizes, p), HX_ERANGE (an id out of range). */
+hx_status hx_mesh_nodes_trilinear(int p, int64_t nelem, const int64_t *elem_verts, int64_t nverts,
+                                  const double *verts, const int32_t *elem_nodes, int64_t nnodes,
+                                  double *node_xyz);
+
+/* Create a mesh: element restriction G (libCEED section) plus node coordinates.
+ *   p           polynomial degree, 1..8; (p+1)^3 nodes per element
+ *   nelem       number of elements, >= 1, with nelem*(p+1)^3 < 2^31
+ *   nnodes      number of L-vector nodes, 1 .. 2^31-1
+ *   elem_nodes  host, nelem*(p+1)^3 int32 node ids, local order
+ *               (i + (p+1)(j + (p+1)k)), i along the reference r1 axis
+ *   node_xyz    host, nnodes*3 FP64 coordinates of the Q_p nodes
+ *   dirichlet   host, nnodes bytes, 1 = constrained node; NULL = none
+ *   out         receives the handle
+ * The library colors the elements so that no two elements of one color share
+ * a node, and orders them internally (color-major, spatially sorted within a
+ * color); this is invisible at the ABI. Device memory: nelem*(p+1)^3*4 bytes
+ * of indices, nelem*(p+1)^2*2 bytes of ownership masks, nnodes*(24+1) bytes.
+ * Errors: HX_EINVAL, HX_ERANGE, HX_ENOMEM, HX_EHIP. */
+hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
+                         const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out);
+
+typedef struct {
+  int p;
+  int ncolors;          /* element colors (launches per apply)                     */
+  int64_t nelem;
+  int64_t nnodes;
+  int64_t nfree;        /* nodes with dirichlet == 0                               */
+  int64_t nuntouched;   /* nodes listed by no element                              */
+  int64_t max_color;    /* elements in the largest color                           */
+} hx_mesh_stats;
+
+hx_status hx_mesh_get_stats(hx_mesh mesh, hx_mesh_stats *stats);
+
+/* Element permutation chosen by the library: order[t] = caller element id of
+ * internal position t; color_start has ncolors+1 entries. Host outputs of
+ * nelem and ncolors+1 entries. */
+hx_status hx_mesh_get_order(hx_mesh mesh, int32_t *order, int64_t *color_start);
+
+void hx_mesh_destroy(hx_mesh mesh);
+
+/* ------------------------------------------------------------------------ */
+/* Bases                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* 1D basis of degree p on the GLL nodes with a q-point rule (Benchmarks
+ * section: q = p+2 Gauss for BP1-BP4, q = p+1 GLL for BP5-BP6).
+ *   qrule = HX_GAUSS: q in {p+1, p+2}; qrule = HX_GLL: q = p+1 (collocated).
+ * Errors: HX_EINVAL (p outside 1..8, q outside the list), HX_ENOMEM. */
+hx_status hx_basis_create(int p, int q, int qrule, hx_basis *out);
+
+/* Host copies of the 1D tables, each optional (NULL = skip):
+ *   nodes[p+1], qpts[q], qweights[q],
+ *   interp[q*(p+1)]  interp[a*(p+1)+i] = l_i(qpts[a]),
+ *   grad[q*(p+1)]    grad[a*(p+1)+i]   = l_i'(qpts[a]). */
+hx_status hx_basis_get_tables(hx_basis basis, double *nodes, double *qpts, double *qweights,
+                              double *interp, double *grad);
+
+void hx_basis_destroy(hx_basis basis);
+
+/* ------------------------------------------------------------------------ */
+/* Operators                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Coefficient kappa(x) = exp(scale * g(x) + shift),
+ * g(x) = sqrt(2/M) sum_m cos(omega_m . x + phase_m): a random-Fourier-feature
+ * Gaussian random field. Not in the paper; it multiplies the diffusion
+ * integrand (A_ij = int kappa grad phi_i . grad phi_j). Host arrays. */
+typedef struct {
+  int M;
+  const double *omega; /* M*3 */
+  const double *phase; /* M   */
+  double scale;
+  double shift;
+} hx_kappa_rff;
+
+/* Create an operator: the pointwise operator D at the quadrature points
+ * (libCEED section) is computed once, in FP64 on the GPU, and stored:
+ *   HX_MASS       w * detJ                          (1 value per point)
+ *   HX_DIFFUSION  w * kappa * detJ * J^-1 J^-T      (6 values per point)
+ * ncomp is 1 (BP1/3/5) or 3 (BP2/4/6). kappa may be NULL (kappa = 1); it is
+ * rejected for HX_MASS. Enqueued on s; returns after setup completes.
+ * Errors: HX_EINVAL, HX_EUNSUPPORTED (p of mesh and basis differ),
+ * HX_EGEOM (detJ <= 0 at some point), HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const hx_kappa_rff *kappa,
+                       hx_stream s, hx_op *out);
+
+/* y = A x on the whole L-vector (no boundary condition), FP64.
+ * x, y: device, nnodes*ncomp doubles. y is overwritten. Asynchronous.
+ * Deterministic: the same x gives bit-identical y on every call.
+ * Errors: HX_EINVAL (null), HX_EHIP. */
+hx_status hx_op_apply(hx_op op, const double *x, double *y, hx_stream s);
+
+/* y = A x in FP32 vectors. qdata_prec = HX_FP64 reads the FP64 geometric
+ * factors and rounds them in registers; HX_FP32 reads an FP32 copy made at
+ * the first such call (FP64 arithmetic, then rounded). Products and sums are
+ * FP32. x, y: device floats. Asynchronous. Errors: HX_EINVAL, HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_apply_f32(hx_op op, int qdata_prec, const float *x, float *y, hx_stream s);
+
+/* y = A x with the basis contractions on bf16 matrix cores (operands rounded
+ * to bfloat16, FP32 accumulation), the pointwise operator in FP32. x, y:
+ * device floats. For HX_DIFFUSION, ncomp = 1. Asynchronous.
+ * Errors: HX_EINVAL, HX_EUNSUPPORTED, HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_apply_bf16(hx_op op, const float *x, float *y, hx_stream s);
+
+/* E-vector action (the bake-off kernel: the element-local part only):
+ * y_e[(e*ncomp + c)*(p+1)^3 + l] = (A_e x_e)_l for caller element e, FP64.
+ * y_e: device, nelem*ncomp*(p+1)^3 doubles. Asynchronous. */
+hx_status hx_op_apply_elem(hx_op op, const double *x, double *y_e, hx_stream s);
+
+/* Diagonal of the assembled operator, matrix-free: diag = G^T diag(B^T D B),
+ * summed over elements (Miniapps section: Nekbone's diagonal preconditioner).
+ * diag: device, nnodes*ncomp doubles, overwritten. Asynchronous. */
+hx_status hx_op_diagonal(hx_op op, double *diag, hx_stream s);
+
+typedef struct {
+  int p, q, qrule, kind, ncomp;
+  int64_t nnodes, nelem;
+  int64_t qdata_bytes;   /* FP64 geometric factors                       */
+  int64_t index_bytes;   /* element restriction indices                  */
+} hx_op_stats;
+
+hx_status hx_op_get_stats(hx_op op, hx_op_stats *stats);
+
+void hx_op_destroy(hx_op op);
+
+/* ------------------------------------------------------------------------ */
+/* Solves                                                                    */
+/* ------------------------------------------------------------------------ */
+
+enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2 };
+enum { HX_SOLVE_FP64 = 0, HX_SOLVE_IR = 1 };
+
+typedef struct {
+  int mode;            /* HX_SOLVE_FP64: FP64 PCG. HX_SOLVE_IR: FP64 iterative
+                          refinement around an FP32 inner PCG                 */
+  int precond;         /* HX_PC_*                                            */
+  double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 (free nodes) */
+  int maxit;           /* iteration cap (outer cap for IR)                    */
+  int check_every;     /* host convergence check period (>= 1)               */
+  int use_x0;          /* 1: x holds the initial guess; 0: start from x = 0   */
+  int cheb_degree;     /* Chebyshev steps per application (>= 1)             */
+  double cheb_ratio;   /* lam_lo = lam_hi / cheb_ratio                        */
+  int cheb_prec;       /* operator precision in the Chebyshev polynomial:
+                          HX_FP64, HX_FP32 or HX_BF16                          */
+  int lanczos_steps;   /* steps of the lam_max estimate (>= 2)               */
+  double inner_rtol;   /* IR: inner FP32 solve tolerance                      */
+  int inner_maxit;     /* IR: inner iteration cap per outer step              */
+  int inner_qdata;     /* IR: HX_FP64 or HX_FP32 geometric factors            */
+} hx_solve_opts;
+
+typedef struct {
+  int iterations;        /* PCG iterations (sum of inner iterations for IR)  */
+  int outer_iterations;  /* IR refinement steps (0 for FP64 PCG)             */
+  int operator_applies;  /* applies of A in any precision                    */
+  double rel_residual;   /* recurrence residual at exit                      */
+  double true_rel_residual; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
+  double lam_max;        /* Chebyshev: estimated lambda_max of D^-1 A         */
+  double setup_seconds;  /* Chebyshev lambda estimate, diagonal               */
+  double solve_seconds;  /* wall time of the iteration                        */
+} hx_solve_info;
+
+/* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
+ * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
+ * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata. */
+void hx_solve_opts_default(hx_solve_opts *opts);
+
+/* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:
+ * homogeneous Dirichlet conditions; CG), preconditioned as opts says.
+ *   b, x: device FP64 L-vectors (nnodes*ncomp); b's constrained entries are
+ *         ignored; x is overwritten (constrained entries set to 0).
+ * Synchronous: returns once x is final; the host reads 8 bytes every
+ * check_every iterations. Uses work vectors owned by op (allocated on first
+ * use, about 8 vectors of nnodes*ncomp doubles).
+ * Errors: HX_EINVAL, HX_ENOCONV (maxit reached; info filled),
+ * HX_EBREAKDOWN, HX_ENOMEM, HX_EHIP. */
+hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
+                       hx_solve_info *info, hx_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEXPA_H */

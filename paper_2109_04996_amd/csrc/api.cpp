@@ -1,0 +1,193 @@
+// C ABI: error reporting, bases, operators and applies.
+#include <cstring>
+#include <string>
+
+#include "hx_internal.h"
+
+namespace hx {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+hx_status fail(hx_status code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+hx_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return e == hipErrorOutOfMemory ? HX_ENOMEM : HX_EHIP;
+}
+
+template <int P>
+hx_status launch_apply_P(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s);
+
+hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyArgs &a, hipStream_t s) {
+  switch (op.P) {
+    case 2: return launch_apply_P<2>(op, prec, out_elem, a, s);
+    case 3: return launch_apply_P<3>(op, prec, out_elem, a, s);
+    case 4: return launch_apply_P<4>(op, prec, out_elem, a, s);
+    case 5: return launch_apply_P<5>(op, prec, out_elem, a, s);
+    case 6: return launch_apply_P<6>(op, prec, out_elem, a, s);
+    case 7: return launch_apply_P<7>(op, prec, out_elem, a, s);
+    case 8: return launch_apply_P<8>(op, prec, out_elem, a, s);
+    case 9: return launch_apply_P<9>(op, prec, out_elem, a, s);
+  }
+  return fail(HX_EUNSUPPORTED, "p out of range");
+}
+
+hx_status make_qdata32(hx_op_s &op, hipStream_t s);
+
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" const char *hx_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *hx_version(void) { return "hexpa 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ bases
+extern "C" hx_status hx_basis_create(int p, int q, int qrule, hx_basis *out) {
+  if (!out) return fail(HX_EINVAL, "out is null");
+  *out = nullptr;
+  auto *b = new (std::nothrow) hx_basis_s();
+  if (!b) return fail(HX_ENOMEM, "host allocation failed");
+  std::string err;
+  if (!make_basis(p, q, qrule, b->b, err)) {
+    delete b;
+    return fail(HX_EINVAL, err);
+  }
+  *out = b;
+  return HX_OK;
+}
+
+extern "C" hx_status hx_basis_get_tables(hx_basis basis, double *nodes, double *qpts, double *qweights,
+                                         double *interp, double *grad) {
+  if (!basis) return fail(HX_EINVAL, "null basis");
+  const Basis1D &b = basis->b;
+  if (nodes) std::memcpy(nodes, b.nodes.data(), sizeof(double) * b.nodes.size());
+  if (qpts) std::memcpy(qpts, b.qpts.data(), sizeof(double) * b.qpts.size());
+  if (qweights) std::memcpy(qweights, b.qw.data(), sizeof(double) * b.qw.size());
+  if (interp) std::memcpy(interp, b.interp.data(), sizeof(double) * b.interp.size());
+  if (grad) std::memcpy(grad, b.grad.data(), sizeof(double) * b.grad.size());
+  return HX_OK;
+}
+
+extern "C" void hx_basis_destroy(hx_basis basis) { delete basis; }
+
+// ------------------------------------------------------------------ operators
+extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const hx_kappa_rff *kappa,
+                                  hx_stream stream, hx_op *out) {
+  if (!out) return fail(HX_EINVAL, "out is null");
+  *out = nullptr;
+  if (!mesh || !basis) return fail(HX_EINVAL, "null mesh or basis");
+  if (kind != HX_MASS && kind != HX_DIFFUSION) return fail(HX_EINVAL, "kind must be HX_MASS or HX_DIFFUSION");
+  if (ncomp != 1 && ncomp != 3) return fail(HX_EINVAL, "ncomp must be 1 or 3");
+  if (basis->b.p != mesh->p) return fail(HX_EUNSUPPORTED, "basis degree differs from the mesh degree");
+  if (kappa && kind == HX_MASS) return fail(HX_EINVAL, "a coefficient applies to HX_DIFFUSION only");
+  if (kappa && (kappa->M < 0 || (kappa->M > 0 && (!kappa->omega || !kappa->phase))))
+    return fail(HX_EINVAL, "kappa: M >= 0 and omega/phase non-null");
+  if (kind == HX_MASS && basis->b.rule == HX_GLL && basis->b.q == basis->b.P) {
+    // collocated mass is diagonal: handled by the interpolation kernel with an identity table
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HX_HIP(hipGetDevice(&dev));
+  if (dev != mesh->device) return fail(HX_EINVAL, "current device differs from the mesh's device");
+
+  auto *op = new (std::nothrow) hx_op_s();
+  if (!op) return fail(HX_ENOMEM, "host allocation failed");
+  op->mesh = mesh;
+  op->b = basis->b;
+  op->kind = kind;
+  op->ncomp = ncomp;
+  op->P = op->b.P;
+  op->Q = op->b.q;
+  op->colloc = (kind == HX_DIFFUSION && op->b.rule == HX_GLL && op->Q == op->P);
+  op->ncq = kind == HX_MASS ? 1 : 6;
+  const int64_t Q3 = (int64_t)op->Q * op->Q * op->Q;
+
+  // device tables: collocated D [P][P]; otherwise interp [Q][P] then the q-point derivative [Q][Q]
+  std::vector<double> tab;
+  if (op->colloc) {
+    tab = op->b.grad;
+  } else {
+    tab = op->b.interp;
+    tab.insert(tab.end(), op->b.colloc.begin(), op->b.colloc.end());
+  }
+  std::vector<float> tab32(tab.begin(), tab.end());
+  hipError_t e;
+  if ((e = op->tab.upload(tab.data(), tab.size())) != hipSuccess ||
+      (e = op->tab32.upload(tab32.data(), tab32.size())) != hipSuccess ||
+      (e = op->qdata.alloc((size_t)mesh->nelem * op->ncq * Q3)) != hipSuccess) {
+    delete op;
+    return hip_fail(e, "operator allocation");
+  }
+  int bad = 0;
+  if (hx_status st = launch_setup_qdata(*op, kappa, s, &bad)) {
+    delete op;
+    return st;
+  }
+  if (bad) {
+    delete op;
+    return fail(HX_EGEOM, "non-positive Jacobian determinant at a quadrature point");
+  }
+  *out = op;
+  return HX_OK;
+}
+
+extern "C" hx_status hx_op_apply(hx_op op, const double *x, double *y, hx_stream s) {
+  if (!op || !x || !y) return fail(HX_EINVAL, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(s);
+  if (op->mesh->nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(double) * op->mesh->nnodes * op->ncomp, st));
+  ApplyArgs a{op->mesh->idx.ptr, op->mesh->own.ptr, nullptr, nullptr, nullptr, x, y, nullptr, 0, 0, op->mesh->nnodes};
+  return launch_apply(*op, Prec::F64, false, a, st);
+}
+
+extern "C" hx_status hx_op_apply_f32(hx_op op, int qdata_prec, const float *x, float *y, hx_stream s) {
+  if (!op || !x || !y) return fail(HX_EINVAL, "null argument");
+  if (qdata_prec != HX_FP64 && qdata_prec != HX_FP32) return fail(HX_EINVAL, "qdata_prec must be HX_FP64 or HX_FP32");
+  hipStream_t st = static_cast<hipStream_t>(s);
+  if (qdata_prec == HX_FP32)
+    if (hx_status e = make_qdata32(*op, st)) return e;
+  if (op->mesh->nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(float) * op->mesh->nnodes * op->ncomp, st));
+  ApplyArgs a{op->mesh->idx.ptr, op->mesh->own.ptr, nullptr, nullptr, nullptr, x, y, nullptr, 0, 0, op->mesh->nnodes};
+  return launch_apply(*op, qdata_prec == HX_FP32 ? Prec::F32_Q32 : Prec::F32_Q64, false, a, st);
+}
+
+extern "C" hx_status hx_op_apply_bf16(hx_op op, const float *x, float *y, hx_stream s) {
+  if (!op || !x || !y) return fail(HX_EINVAL, "null argument");
+  if (op->kind != HX_DIFFUSION || op->ncomp != 1) return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
+  return launch_apply_bf16(*op, x, y, static_cast<hipStream_t>(s));
+}
+
+extern "C" hx_status hx_op_apply_elem(hx_op op, const double *x, double *y_e, hx_stream s) {
+  if (!op || !x || !y_e) return fail(HX_EINVAL, "null argument");
+  ApplyArgs a{op->mesh->idx.ptr, op->mesh->own.ptr, nullptr, nullptr, nullptr, x, y_e, op->mesh->order_d.ptr, 0, 0,
+              op->mesh->nnodes};
+  return launch_apply(*op, Prec::F64, true, a, static_cast<hipStream_t>(s));
+}
+
+extern "C" hx_status hx_op_diagonal(hx_op op, double *diag, hx_stream s) {
+  if (!op || !diag) return fail(HX_EINVAL, "null argument");
+  return launch_diagonal(*op, diag, static_cast<hipStream_t>(s));
+}
+
+extern "C" hx_status hx_op_get_stats(hx_op op, hx_op_stats *st) {
+  if (!op || !st) return fail(HX_EINVAL, "null argument");
+  st->p = op->b.p;
+  st->q = op->Q;
+  st->qrule = op->b.rule;
+  st->kind = op->kind;
+  st->ncomp = op->ncomp;
+  st->nnodes = op->mesh->nnodes;
+  st->nelem = op->mesh->nelem;
+  st->qdata_bytes = (int64_t)op->qdata.count * 8;
+  st->index_bytes = (int64_t)op->mesh->idx.count * 4;
+  return HX_OK;
+}
+
+extern "C" void hx_op_destroy(hx_op op) { delete op; }

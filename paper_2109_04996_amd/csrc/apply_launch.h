@@ -1,0 +1,60 @@
+// Host-side launch of the fused apply: one launch per element color, in color order.
+#pragma once
+
+#include "apply_kernel.h"
+#include "hx_internal.h"
+
+namespace hx {
+
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
+hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
+  constexpr int EPB = EpbOf<Q>::v;
+  const hx_mesh_s &m = *op.mesh;
+  for (int c = 0; c < m.ncolors; ++c) {
+    const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
+    if (e1 <= e0) continue;
+    const int64_t nb = (e1 - e0 + EPB - 1) / EPB;
+    hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s, a.idx,
+                       a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_apply launch");
+  return HX_OK;
+}
+
+template <int P, int Q, int MODE, int NC>
+hx_status launch_prec(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
+  if (eout) {
+    if (prec != Prec::F64) return fail(HX_EUNSUPPORTED, "E-vector output is FP64 only");
+    return launch_colors<P, Q, MODE, NC, double, double, true>(op, op.tab.ptr, op.qdata.ptr, a, s);
+  }
+  switch (prec) {
+    case Prec::F64:
+      return launch_colors<P, Q, MODE, NC, double, double, false>(op, op.tab.ptr, op.qdata.ptr, a, s);
+    case Prec::F32_Q64:
+      return launch_colors<P, Q, MODE, NC, float, double, false>(op, op.tab32.ptr, op.qdata.ptr, a, s);
+    case Prec::F32_Q32:
+      return launch_colors<P, Q, MODE, NC, float, float, false>(op, op.tab32.ptr, op.qdata32.ptr, a, s);
+  }
+  return fail(HX_EINVAL, "bad precision");
+}
+
+template <int P, int Q, int MODE>
+hx_status launch_nc(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
+  if (op.ncomp == 1) return launch_prec<P, Q, MODE, 1>(op, prec, eout, a, s);
+  if (op.ncomp == 3) return launch_prec<P, Q, MODE, 3>(op, prec, eout, a, s);
+  return fail(HX_EINVAL, "ncomp must be 1 or 3");
+}
+
+template <int P>
+hx_status launch_apply_P(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
+  if (op.colloc) return launch_nc<P, P, MODE_COLLOC>(op, prec, eout, a, s);
+  const bool mass = op.kind == HX_MASS;
+  if (op.Q == P) return mass ? launch_nc<P, P, MODE_MASS>(op, prec, eout, a, s)
+                             : launch_nc<P, P, MODE_DIFF>(op, prec, eout, a, s);
+  if (op.Q == P + 1) return mass ? launch_nc<P, P + 1, MODE_MASS>(op, prec, eout, a, s)
+                                 : launch_nc<P, P + 1, MODE_DIFF>(op, prec, eout, a, s);
+  return fail(HX_EUNSUPPORTED, "q must be p+1 or p+2");
+}
+
+}  // namespace hx

@@ -1,0 +1,134 @@
+// Internal declarations shared by the hexpa sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hexpa.h"
+
+namespace hx {
+
+constexpr int kMaxP = 9;   // nodes per direction (degree 8)
+constexpr int kMaxQ = 10;  // quadrature points per direction
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+hx_status fail(hx_status code, const std::string &msg);
+hx_status hip_fail(hipError_t e, const char *what);
+
+#define HX_HIP(call)                                   \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) return hx::hip_fail(_e, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- device buffers
+template <typename T>
+struct DevBuf {
+  T *ptr = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    count = 0;
+  }
+  hipError_t alloc(size_t n) {
+    release();
+    count = n;
+    if (n == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void **>(&ptr), n * sizeof(T));
+  }
+  hipError_t upload(const T *h, size_t n) {
+    hipError_t e = alloc(n);
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpy(ptr, h, n * sizeof(T), hipMemcpyHostToDevice);
+  }
+};
+
+// ---------------------------------------------------------------- 1D basis (host, FP64)
+struct Basis1D {
+  int p = 0, P = 0, q = 0, rule = HX_GAUSS;
+  std::vector<double> nodes, qpts, qw;
+  std::vector<double> interp;  // [q][P]
+  std::vector<double> grad;    // [q][P]
+  std::vector<double> colloc;  // [q][q]: derivative of the Lagrange basis on the q points, at those points
+};
+
+bool make_basis(int p, int q, int rule, Basis1D &out, std::string &err);
+void gll_nodes_weights(int p, std::vector<double> &x, std::vector<double> &w);
+void gauss_nodes_weights(int q, std::vector<double> &x, std::vector<double> &w);
+void lagrange_tables(const std::vector<double> &nodes, const std::vector<double> &pts,
+                     std::vector<double> &val, std::vector<double> &der);
+
+}  // namespace hx
+
+struct hx_basis_s {
+  hx::Basis1D b;
+};
+
+struct hx_mesh_s {
+  int p = 0, P = 0, device = 0;
+  int64_t nelem = 0, nnodes = 0, nfree = 0, nuntouched = 0;
+  int ncolors = 0;
+  std::vector<int32_t> order;        // internal position -> caller element id
+  std::vector<int64_t> color_start;  // ncolors + 1
+  std::vector<double> h_xyz;         // nnodes*3
+  hx::DevBuf<int32_t> idx;           // [E_internal][P^3] node ids
+  hx::DevBuf<uint16_t> own;          // [E_internal][P^2] bit k: this element writes node (i,j,k) first
+  hx::DevBuf<int32_t> order_d;       // internal position -> caller element id
+  hx::DevBuf<double> xyz;            // nnodes*3
+  hx::DevBuf<uint8_t> freemask;      // nnodes, 1 = free node
+};
+
+struct hx_op_s {
+  hx_mesh mesh = nullptr;
+  hx::Basis1D b;
+  int kind = 0, ncomp = 1, P = 0, Q = 0;
+  bool colloc = false;  // diffusion on the GLL nodes: no interpolation step
+  int ncq = 1;          // stored values per quadrature point
+  hx::DevBuf<double> qdata;    // [E_internal][ncq][Q^3]
+  hx::DevBuf<float> qdata32;   // FP32 copy, made on demand
+  hx::DevBuf<double> tab;      // device 1D tables: interp [Q][P], grad [Q][P], colloc [Q][Q]
+  hx::DevBuf<float> tab32;
+  // solver workspace (allocated on first solve)
+  hx::DevBuf<double> work;
+  hx::DevBuf<float> work32;
+  hx::DevBuf<double> red;      // reduction partials and device scalars
+  hx::DevBuf<double> diag;     // assembled diagonal (cached)
+  bool diag_valid = false;
+  // bf16 operator tables (made on demand)
+  hx::DevBuf<uint16_t> tab_bf16;
+};
+
+namespace hx {
+
+// ---------------------------------------------------------------- kernels (launchers)
+struct ApplyArgs {
+  const int32_t *idx;
+  const uint16_t *own;
+  const void *qd;       // double or float
+  const double *tab;    // device tables (double)
+  const float *tab32;
+  const void *x;
+  void *y;
+  const int32_t *order;  // for E-vector output
+  int64_t e_begin, e_end;
+  int64_t nnodes;
+};
+
+enum class Prec { F64, F32_Q64, F32_Q32 };
+
+// one launch per color; out_elem: write the E-vector instead of scattering
+hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyArgs &a, hipStream_t s);
+hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s, int *bad_det);
+hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
+hx_status launch_apply_bf16(hx_op_s &op, const float *x, float *y, hipStream_t s);
+
+}  // namespace hx

@@ -1,0 +1,297 @@
+// Mesh ingestion: validation, element coloring and ordering, ownership masks.
+//
+// libCEED section (operator decomposition): the element restriction G maps the
+// L-vector to per-element values through an index array; its transpose G^T
+// sums element contributions back into the L-vector. The fused apply does
+// G^T without atomics: elements are split into colors so that no two
+// elements of one color share a node, colors run one launch after another,
+// and inside a launch every node is written by at most one element. The
+// first element to touch a node (in color order) stores its value, later
+// elements read-modify-write it; the per-element ownership bitmask built here
+// says which of the two each element-local node takes.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "hx_internal.h"
+
+namespace {
+
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+struct Centroids {
+  std::vector<double> c;  // E*3
+  double lo[3], hi[3];
+};
+
+Centroids centroids(int P, int64_t E, const int32_t *en, const double *xyz) {
+  Centroids C;
+  C.c.assign((size_t)E * 3, 0.0);
+  const int p = P - 1;
+  const int corner[8] = {0, p, p * P, p + p * P, p * P * P, p + p * P * P, p * P + p * P * P,
+                         p + p * P + p * P * P};
+  for (int d = 0; d < 3; ++d) {
+    C.lo[d] = 1e300;
+    C.hi[d] = -1e300;
+  }
+  for (int64_t e = 0; e < E; ++e) {
+    for (int v = 0; v < 8; ++v) {
+      const int64_t n = en[(size_t)e * P * P * P + corner[v]];
+      for (int d = 0; d < 3; ++d) C.c[e * 3 + d] += 0.125 * xyz[n * 3 + d];
+    }
+    for (int d = 0; d < 3; ++d) {
+      C.lo[d] = std::min(C.lo[d], C.c[e * 3 + d]);
+      C.hi[d] = std::max(C.hi[d], C.c[e * 3 + d]);
+    }
+  }
+  return C;
+}
+
+std::vector<uint64_t> morton_keys(const Centroids &C, int64_t E) {
+  std::vector<uint64_t> k(E);
+  for (int64_t e = 0; e < E; ++e) {
+    uint64_t q[3];
+    for (int d = 0; d < 3; ++d) {
+      double span = C.hi[d] - C.lo[d];
+      double t = span > 0 ? (C.c[e * 3 + d] - C.lo[d]) / span : 0.0;
+      q[d] = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(t * 2097151.0)));
+    }
+    k[e] = spread3(q[0]) | spread3(q[1]) << 1 | spread3(q[2]) << 2;
+  }
+  return k;
+}
+
+// Greedy distance-1 coloring of the element-node graph in the given visiting order.
+int greedy_color(int P3, int64_t nnodes, const int32_t *en, const std::vector<int64_t> &visit,
+                 std::vector<int> &color) {
+  const int64_t E = (int64_t)visit.size();
+  color.assign(E, -1);
+  std::vector<uint64_t> used(nnodes, 0);  // colors 0..63 used at each node
+  int ncol = 0;
+  std::vector<std::vector<uint8_t>> hi_used;  // colors >= 64 (rare), per node, allocated on demand
+  for (int64_t t = 0; t < E; ++t) {
+    const int64_t e = visit[t];
+    const int32_t *nd = en + (size_t)e * P3;
+    uint64_t forb = 0;
+    for (int l = 0; l < P3; ++l) forb |= used[nd[l]];
+    int c;
+    if (~forb != 0) {
+      c = __builtin_ctzll(~forb);
+    } else {
+      // slow path: search colors >= 64
+      if (hi_used.empty()) hi_used.resize(nnodes);
+      c = 64;
+      for (;; ++c) {
+        bool ok = true;
+        for (int l = 0; l < P3 && ok; ++l) {
+          const auto &h = hi_used[nd[l]];
+          if ((int)h.size() > c - 64 && h[c - 64]) ok = false;
+        }
+        if (ok) break;
+      }
+    }
+    color[e] = c;
+    for (int l = 0; l < P3; ++l) {
+      if (c < 64) {
+        used[nd[l]] |= 1ULL << c;
+      } else {
+        auto &h = hi_used[nd[l]];
+        if ((int)h.size() <= c - 64) h.resize(c - 63, 0);
+        h[c - 64] = 1;
+      }
+    }
+    ncol = std::max(ncol, c + 1);
+  }
+  return ncol;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_mesh_nodes_trilinear(int p, int64_t nelem, const int64_t *elem_verts, int64_t nverts,
+                                             const double *verts, const int32_t *elem_nodes, int64_t nnodes,
+                                             double *node_xyz) {
+  if (p < 1 || p > hx::kMaxP - 1) return hx::fail(HX_EINVAL, "p must be in 1..8");
+  if (!elem_verts || !verts || !elem_nodes || !node_xyz) return hx::fail(HX_EINVAL, "null pointer");
+  if (nelem < 1 || nverts < 1 || nnodes < 1) return hx::fail(HX_EINVAL, "sizes must be positive");
+  const int P = p + 1, P3 = P * P * P;
+  std::vector<double> x, w;
+  hx::gll_nodes_weights(p, x, w);
+  std::fill(node_xyz, node_xyz + nnodes * 3, 0.0);
+  for (int64_t e = 0; e < nelem; ++e) {
+    double V[8][3];
+    for (int v = 0; v < 8; ++v) {
+      int64_t id = elem_verts[e * 8 + v];
+      if (id < 0 || id >= nverts) return hx::fail(HX_ERANGE, "vertex id out of range");
+      for (int d = 0; d < 3; ++d) V[v][d] = verts[id * 3 + d];
+    }
+    for (int k = 0; k < P; ++k)
+      for (int j = 0; j < P; ++j)
+        for (int i = 0; i < P; ++i) {
+          const double r[3] = {x[i], x[j], x[k]};
+          double pt[3] = {0, 0, 0};
+          for (int v = 0; v < 8; ++v) {
+            double N = 1.0;
+            for (int d = 0; d < 3; ++d) {
+              const int bit = (v >> d) & 1;
+              N *= 0.5 * (1.0 + (bit ? r[d] : -r[d]));
+            }
+            for (int d = 0; d < 3; ++d) pt[d] += N * V[v][d];
+          }
+          const int64_t n = elem_nodes[e * P3 + i + P * (j + P * k)];
+          if (n < 0 || n >= nnodes) return hx::fail(HX_ERANGE, "node id out of range");
+          for (int d = 0; d < 3; ++d) node_xyz[n * 3 + d] = pt[d];
+        }
+  }
+  return HX_OK;
+}
+
+extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
+                                    const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out) {
+  if (!out) return hx::fail(HX_EINVAL, "out is null");
+  *out = nullptr;
+  if (p < 1 || p > hx::kMaxP - 1) return hx::fail(HX_EINVAL, "p must be in 1..8");
+  if (!elem_nodes || !node_xyz) return hx::fail(HX_EINVAL, "elem_nodes and node_xyz must not be null");
+  const int P = p + 1, P2 = P * P, P3 = P2 * P;
+  if (nelem < 1 || nnodes < 1 || nnodes > INT32_MAX) return hx::fail(HX_EINVAL, "nelem/nnodes out of range");
+  if (nelem * (int64_t)P3 >= ((int64_t)1 << 31)) return hx::fail(HX_EINVAL, "nelem*(p+1)^3 must be < 2^31");
+  for (int64_t t = 0; t < nelem * P3; ++t)
+    if (elem_nodes[t] < 0 || elem_nodes[t] >= nnodes)
+      return hx::fail(HX_ERANGE, "elem_nodes entry " + std::to_string(t) + " = " + std::to_string(elem_nodes[t]) +
+                                     " outside [0, nnodes)");
+
+  auto *m = new (std::nothrow) hx_mesh_s();
+  if (!m) return hx::fail(HX_ENOMEM, "host allocation failed");
+  m->p = p;
+  m->P = P;
+  m->nelem = nelem;
+  m->nnodes = nnodes;
+  (void)hipGetDevice(&m->device);
+  m->h_xyz.assign(node_xyz, node_xyz + nnodes * 3);
+
+  // coloring: greedy in two visiting orders (Morton of centroids; centroid z-y-x rows),
+  // keep the one with fewer colors
+  Centroids C = centroids(P, nelem, elem_nodes, node_xyz);
+  std::vector<uint64_t> mk = morton_keys(C, nelem);
+  std::vector<int64_t> v1(nelem), v2(nelem);
+  std::iota(v1.begin(), v1.end(), 0);
+  std::iota(v2.begin(), v2.end(), 0);
+  std::stable_sort(v1.begin(), v1.end(), [&](int64_t a, int64_t b) { return mk[a] < mk[b]; });
+  {
+    // rows: quantize each centroid coordinate with a step of about half an element size
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) vol *= std::max(C.hi[d] - C.lo[d], 1e-300);
+    double h = 0.5 * std::cbrt(vol / (double)nelem);
+    std::vector<int64_t> key(nelem * 3);
+    for (int64_t e = 0; e < nelem; ++e)
+      for (int d = 0; d < 3; ++d) key[e * 3 + d] = (int64_t)std::floor((C.c[e * 3 + d] - C.lo[d]) / h);
+    std::stable_sort(v2.begin(), v2.end(), [&](int64_t a, int64_t b) {
+      for (int d = 2; d >= 0; --d)
+        if (key[a * 3 + d] != key[b * 3 + d]) return key[a * 3 + d] < key[b * 3 + d];
+      return false;
+    });
+  }
+  std::vector<int> col1, col2;
+  int n1 = greedy_color(P3, nnodes, elem_nodes, v1, col1);
+  int n2 = greedy_color(P3, nnodes, elem_nodes, v2, col2);
+  std::vector<int> &col = (n2 <= n1) ? col2 : col1;
+  const int ncol = std::min(n1, n2);
+  m->ncolors = ncol;
+
+  // internal order: color-major, Morton order inside a color
+  m->order.resize(nelem);
+  std::iota(m->order.begin(), m->order.end(), 0);
+  std::stable_sort(m->order.begin(), m->order.end(), [&](int32_t a, int32_t b) {
+    if (col[a] != col[b]) return col[a] < col[b];
+    return mk[a] < mk[b];
+  });
+  m->color_start.assign(ncol + 1, 0);
+  for (int64_t e = 0; e < nelem; ++e) m->color_start[col[e] + 1]++;
+  for (int c = 0; c < ncol; ++c) m->color_start[c + 1] += m->color_start[c];
+
+  // indices and ownership in internal order
+  std::vector<int32_t> idx((size_t)nelem * P3);
+  std::vector<uint16_t> own((size_t)nelem * P2, 0);
+  std::vector<uint8_t> seen(nnodes, 0);
+  for (int64_t t = 0; t < nelem; ++t) {
+    const int32_t *src = elem_nodes + (size_t)m->order[t] * P3;
+    std::copy(src, src + P3, idx.begin() + (size_t)t * P3);
+    for (int k = 0; k < P; ++k)
+      for (int ij = 0; ij < P2; ++ij) {
+        const int32_t n = src[ij + P2 * k];
+        if (!seen[n]) {
+          seen[n] = 1;
+          own[(size_t)t * P2 + ij] |= (uint16_t)(1u << k);
+        }
+      }
+  }
+  m->nuntouched = 0;
+  for (int64_t n = 0; n < nnodes; ++n) m->nuntouched += seen[n] ? 0 : 1;
+
+  // sanity: a node appears at most once per color
+  {
+    std::vector<int32_t> last(nnodes, -1);
+    for (int c = 0; c < ncol; ++c)
+      for (int64_t t = m->color_start[c]; t < m->color_start[c + 1]; ++t)
+        for (int l = 0; l < P3; ++l) {
+          const int32_t n = idx[(size_t)t * P3 + l];
+          if (last[n] == c) {
+            // an element lists the same node twice, or the coloring is wrong
+            delete m;
+            return hx::fail(HX_EINVAL, "element lists a node more than once, or two elements of one color share a node");
+          }
+          last[n] = c;
+        }
+  }
+
+  std::vector<uint8_t> fm(nnodes, 1);
+  m->nfree = nnodes;
+  if (dirichlet) {
+    m->nfree = 0;
+    for (int64_t n = 0; n < nnodes; ++n) {
+      fm[n] = dirichlet[n] ? 0 : 1;
+      m->nfree += fm[n];
+    }
+  }
+  hipError_t e;
+  if ((e = m->idx.upload(idx.data(), idx.size())) != hipSuccess ||
+      (e = m->own.upload(own.data(), own.size())) != hipSuccess ||
+      (e = m->order_d.upload(m->order.data(), m->order.size())) != hipSuccess ||
+      (e = m->xyz.upload(node_xyz, (size_t)nnodes * 3)) != hipSuccess ||
+      (e = m->freemask.upload(fm.data(), fm.size())) != hipSuccess) {
+    delete m;
+    return hx::hip_fail(e, "mesh upload");
+  }
+  *out = m;
+  return HX_OK;
+}
+
+extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
+  if (!m || !s) return hx::fail(HX_EINVAL, "null pointer");
+  s->p = m->p;
+  s->ncolors = m->ncolors;
+  s->nelem = m->nelem;
+  s->nnodes = m->nnodes;
+  s->nfree = m->nfree;
+  s->nuntouched = m->nuntouched;
+  s->max_color = 0;
+  for (int c = 0; c < m->ncolors; ++c)
+    s->max_color = std::max<int64_t>(s->max_color, m->color_start[c + 1] - m->color_start[c]);
+  return HX_OK;
+}
+
+extern "C" hx_status hx_mesh_get_order(hx_mesh m, int32_t *order, int64_t *color_start) {
+  if (!m) return hx::fail(HX_EINVAL, "null mesh");
+  if (order) std::copy(m->order.begin(), m->order.end(), order);
+  if (color_start) std::copy(m->color_start.begin(), m->color_start.end(), color_start);
+  return HX_OK;
+}
+
+extern "C" void hx_mesh_destroy(hx_mesh m) { delete m; }

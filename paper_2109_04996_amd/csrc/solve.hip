@@ -1,0 +1,649 @@
+// Preconditioned conjugate gradients on the GPU.
+//
+// Benchmarks section: the bake-off problems are CG solves of the Dirichlet
+// problem; CG mixes the local operator work with global reductions (two dot
+// products per iteration). Miniapps section (Nekbone): CG with a diagonal
+// preconditioner. Here the scalars alpha, beta, r'z, p'Ap stay in device
+// memory: every iteration is a fixed sequence of kernels on the caller's
+// stream, and the host reads a few bytes every check_every iterations.
+//
+// Reductions are deterministic: each block sums a fixed contiguous slice in a
+// fixed order (wavefront shuffles, then LDS), then one block adds the block
+// sums in index order. Products of FP32 vectors are accumulated in FP64.
+//
+// Not in the paper: the Chebyshev polynomial preconditioner (textbook
+// Chebyshev acceleration of D^-1 A, degree k, k-1 operator applies), the
+// Lanczos estimate of lambda_max(D^-1 A) from CG coefficients, and mixed
+// precision iterative refinement (FP64 residual and update, FP32 inner PCG).
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <random>
+
+#include "hx_internal.h"
+
+extern "C" hx_status hx_op_diagonal(hx_op op, double *diag, hx_stream s);
+
+namespace hx {
+
+hx_status make_qdata32(hx_op_s &op, hipStream_t s);
+
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecBlocks = 1024;
+
+enum { S_RZ = 0, S_PAP, S_ALPHA, S_RZNEW, S_BETA, S_RR, S_FLAG, S_BB, S_TMP, S_NSCAL = 16 };
+enum { FIN_SUM = 0, FIN_PAP, FIN_RZ_RR, FIN_RZ };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum in a fixed order, result on every thread
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kVecThreads / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kVecThreads / 64; ++w) s += sh[w];
+  return s;
+}
+
+// contiguous slice of [0, n) for this block: a deterministic partition
+__device__ __forceinline__ void slice(int64_t n, int64_t &lo, int64_t &hi) {
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  lo = min(n, (int64_t)blockIdx.x * per);
+  hi = min(n, lo + per);
+}
+
+template <int NC>
+__device__ __forceinline__ bool is_free(const uint8_t *fm, int64_t t) {
+  return fm[NC == 1 ? t : t / NC] != 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_dot(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+                                                       double *__restrict__ part) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double s = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) s += (double)a[t] * (double)b[t];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// one block: reduce the partials (p1 optional) and derive the CG scalars
+__global__ void __launch_bounds__(kVecThreads) k_final(const double *__restrict__ p0, const double *__restrict__ p1,
+                                                         int nb, double *__restrict__ S, int what, int slot) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    a += p0[i];
+    if (p1) b += p1[i];
+  }
+  a = block_sum(a);
+  if (p1) b = block_sum(b);
+  if (threadIdx.x != 0) return;
+  switch (what) {
+    case FIN_SUM:
+      S[slot] = a;
+      break;
+    case FIN_PAP: {
+      S[S_PAP] = a;
+      const bool ok = a > 0.0 && isfinite(a);
+      S[S_ALPHA] = ok ? S[S_RZ] / a : 0.0;
+      if (!ok) S[S_FLAG] = 1.0;
+      break;
+    }
+    case FIN_RZ_RR: {  // a = r'z of the new residual, b = r'r
+      const double rz_old = S[S_RZ];
+      S[S_RZNEW] = a;
+      S[S_RR] = b;
+      S[S_BETA] = (rz_old != 0.0) ? a / rz_old : 0.0;
+      S[S_RZ] = a;
+      if (!(a > 0.0) && b > 0.0) S[S_FLAG] = 2.0;
+      if (!isfinite(a) || !isfinite(b)) S[S_FLAG] = 3.0;
+      break;
+    }
+    case FIN_RZ:
+      S[S_RZ] = a;
+      if (!(a > 0.0) && S[S_RR] > 0.0) S[S_FLAG] = 2.0;
+      if (!isfinite(a)) S[S_FLAG] = 3.0;
+      break;
+  }
+}
+
+// r = m (scale * b - w), partial r'r; w may be null
+template <typename T, typename TB, int NC>
+__global__ void __launch_bounds__(kVecThreads)
+    k_resid(int64_t n, double scale, const TB *__restrict__ b, const double *__restrict__ w,
+            const uint8_t *__restrict__ fm, T *__restrict__ r, double *__restrict__ part_rr) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double s = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const double v = is_free<NC>(fm, t) ? scale * (double)b[t] - (w ? w[t] : 0.0) : 0.0;
+    const T rv = (T)v;
+    r[t] = rv;
+    s += (double)rv * (double)rv;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// z = dinv r, partial r'z (dinv is 0 on constrained nodes)
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_jacobi(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r,
+                                                          T *__restrict__ z, double *__restrict__ part_rz) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double s = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const T zv = dinv[t] * r[t];
+    z[t] = zv;
+    s += (double)r[t] * (double)zv;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s;
+}
+
+// x += alpha p; r -= alpha m w; with JAC also z = dinv r; partials r'z (JAC) and r'r
+template <typename T, int NC, bool JAC>
+__global__ void __launch_bounds__(kVecThreads)
+    k_update(int64_t n, const double *__restrict__ S, T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r,
+             const T *__restrict__ w, const uint8_t *__restrict__ fm, const T *__restrict__ dinv, T *__restrict__ z,
+             double *__restrict__ part_rz, double *__restrict__ part_rr) {
+  const T alpha = (T)S[S_ALPHA];
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double srz = 0.0, srr = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    x[t] += alpha * p[t];
+    const T rv = is_free<NC>(fm, t) ? r[t] - alpha * w[t] : T(0);
+    r[t] = rv;
+    srr += (double)rv * (double)rv;
+    if constexpr (JAC) {
+      const T zv = dinv[t] * rv;
+      z[t] = zv;
+      srz += (double)rv * (double)zv;
+    }
+  }
+  srr = block_sum(srr);
+  if constexpr (JAC) srz = block_sum(srz);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = srr;
+    if constexpr (JAC) part_rz[blockIdx.x] = srz;
+  }
+}
+
+// p = z + beta p
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_pupd(int64_t n, const double *__restrict__ S, const T *__restrict__ z,
+                                                        T *__restrict__ p) {
+  const T beta = (T)S[S_BETA];
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) p[t] = z[t] + beta * p[t];
+}
+
+// Chebyshev first step: d = dinv r / theta, z = d
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_cheb0(int64_t n, T inv_theta, const T *__restrict__ dinv,
+                                                         const T *__restrict__ r, T *__restrict__ d,
+                                                         T *__restrict__ z) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const T v = inv_theta * dinv[t] * r[t];
+    d[t] = v;
+    z[t] = v;
+  }
+}
+
+// Chebyshev step: d = c1 d + c2 dinv (r - A z), z += d
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_cheb(int64_t n, T c1, T c2, const T *__restrict__ dinv,
+                                                        const T *__restrict__ r, const T *__restrict__ az,
+                                                        T *__restrict__ d, T *__restrict__ z) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const T v = c1 * d[t] + c2 * dinv[t] * (r[t] - az[t]);
+    d[t] = v;
+    z[t] += v;
+  }
+}
+
+// dinv = m / diag, or m alone when diag is null (no preconditioner)
+template <typename T, int NC>
+__global__ void __launch_bounds__(kVecThreads) k_dinv(int64_t n, const double *__restrict__ diag,
+                                                        const uint8_t *__restrict__ fm, T *__restrict__ dinv) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dinv[t] = is_free<NC>(fm, t) ? (diag ? (T)(1.0 / diag[t]) : T(1)) : T(0);
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(kVecThreads) k_convert(int64_t n, double scale, const TA *__restrict__ a,
+                                                           TB *__restrict__ b) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    b[t] = (TB)(scale * (double)a[t]);
+}
+
+// x += scale * d (FP64 x)
+template <typename TD>
+__global__ void __launch_bounds__(kVecThreads) k_axpy(int64_t n, double scale, const TD *__restrict__ d,
+                                                        double *__restrict__ x) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    x[t] += scale * (double)d[t];
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kVecThreads) k_maskset(int64_t n, const uint8_t *__restrict__ fm, double *__restrict__ x) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    if (!is_free<NC>(fm, t)) x[t] = 0.0;
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix (diagonal d, off-diagonal e) by Sturm bisection
+double tridiag_max_eig(const std::vector<double> &d, const std::vector<double> &e) {
+  const int n = (int)d.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+template <typename T>
+struct Vecs {
+  T *r, *z, *p, *w, *dinv, *cd, *ct, *x;
+};
+
+struct Ctx {
+  hx_op_s &op;
+  hipStream_t s;
+  int64_t n;
+  int nc;
+  double *part0, *part1, *S;
+  double *hS;  // pinned host copy of S
+  int applies = 0;
+};
+
+#define LAUNCH_V(kern, ...) hipLaunchKernelGGL(kern, dim3(kVecBlocks), dim3(kVecThreads), 0, c.s, __VA_ARGS__)
+#define FINAL(p0, p1, what, slot) \
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kVecThreads), 0, c.s, p0, p1, kVecBlocks, c.S, (int)(what), (int)(slot))
+
+hx_status apply_T(Ctx &c, const double *x, double *y, int) {
+  ApplyArgs a{c.op.mesh->idx.ptr, c.op.mesh->own.ptr, nullptr, nullptr, nullptr, x, y, nullptr, 0, 0,
+              c.op.mesh->nnodes};
+  if (c.op.mesh->nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(double) * c.n, c.s));
+  ++c.applies;
+  return launch_apply(c.op, Prec::F64, false, a, c.s);
+}
+
+// prec: HX_FP64 (FP64 qdata), HX_FP32 (FP32 qdata), HX_BF16 (matrix-core operator)
+hx_status apply_T(Ctx &c, const float *x, float *y, int prec) {
+  ++c.applies;
+  if (prec == HX_BF16) return launch_apply_bf16(c.op, x, y, c.s);
+  ApplyArgs a{c.op.mesh->idx.ptr, c.op.mesh->own.ptr, nullptr, nullptr, nullptr, x, y, nullptr, 0, 0,
+              c.op.mesh->nnodes};
+  if (c.op.mesh->nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(float) * c.n, c.s));
+  return launch_apply(c.op, prec == HX_FP32 ? Prec::F32_Q32 : Prec::F32_Q64, false, a, c.s);
+}
+
+hx_status read_scalars(Ctx &c) {
+  HX_HIP(hipMemcpyAsync(c.hS, c.S, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, c.s));
+  HX_HIP(hipStreamSynchronize(c.s));
+  return HX_OK;
+}
+
+struct Cheb {
+  int degree = 4;
+  double lam_lo = 0, lam_hi = 0;
+};
+
+// z = s(D^-1 A) D^-1 r: degree steps from z = 0, degree-1 operator applies
+template <typename T>
+hx_status cheb_apply(Ctx &c, const Cheb &ch, const Vecs<T> &v, const T *r, T *z, int op_prec) {
+  const double theta = 0.5 * (ch.lam_hi + ch.lam_lo), delta = 0.5 * (ch.lam_hi - ch.lam_lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  LAUNCH_V((k_cheb0<T>), c.n, (T)(1.0 / theta), v.dinv, r, v.cd, z);
+  for (int k = 1; k < ch.degree; ++k) {
+    if (hx_status st = apply_T(c, z, v.ct, op_prec)) return st;
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    LAUNCH_V((k_cheb<T>), c.n, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), v.dinv, r, v.ct, v.cd, z);
+    rho = rho_new;
+  }
+  HX_HIP(hipGetLastError());
+  return HX_OK;
+}
+
+// Preconditioner that is not fused into the update: computes z from r, then the partial r'z into part0.
+template <typename T>
+using PrecFn = std::function<hx_status(const T *r, T *z)>;
+
+// PCG on vectors of type T. On entry v.r holds the masked right-hand side with r'r = rr0; solves for v.x
+// from 0. Jacobi (and none, with dinv = mask) is fused into the update kernel; other preconditioners
+// go through pc. Stops when r'r <= stop2, at maxit, or on breakdown.
+template <typename T>
+hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, double rr0, double stop2, int maxit,
+                   int check_every, int *iters, double *rr_out) {
+  HX_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * c.n, c.s));
+  HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, c.s));
+  if (!pc) {
+    LAUNCH_V((k_jacobi<T>), c.n, v.dinv, v.r, v.z, c.part0);
+  } else {
+    if (hx_status st = (*pc)(v.r, v.z)) return st;
+    LAUNCH_V((k_dot<T>), c.n, v.r, v.z, c.part0);
+  }
+  FINAL(c.part0, (const double *)nullptr, FIN_RZ, 0);
+  HX_HIP(hipMemcpyAsync(v.p, v.z, sizeof(T) * c.n, hipMemcpyDeviceToDevice, c.s));
+  int it = 0;
+  double rr = rr0;
+  while (it < maxit && rr > stop2) {
+    if (hx_status st = apply_T(c, v.p, v.w, op_prec)) return st;
+    LAUNCH_V((k_dot<T>), c.n, v.p, v.w, c.part0);
+    FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
+    const uint8_t *fm = c.op.mesh->freemask.ptr;
+    if (!pc) {
+      if (c.nc == 1) LAUNCH_V((k_update<T, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+      else LAUNCH_V((k_update<T, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+    } else {
+      if (c.nc == 1) LAUNCH_V((k_update<T, 1, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+      else LAUNCH_V((k_update<T, 3, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+      if (hx_status st = (*pc)(v.r, v.z)) return st;
+      LAUNCH_V((k_dot<T>), c.n, v.r, v.z, c.part0);
+    }
+    FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
+    LAUNCH_V((k_pupd<T>), c.n, c.S, v.z, v.p);
+    HX_HIP(hipGetLastError());
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      if (hx_status e = read_scalars(c)) return e;
+      rr = c.hS[S_RR];
+      if (c.hS[S_FLAG] != 0.0) {
+        *iters = it;
+        *rr_out = rr;
+        return fail(HX_EBREAKDOWN, "CG breakdown: p'Ap <= 0, r'z <= 0 or a non-finite scalar (flag " +
+                                       std::to_string((int)c.hS[S_FLAG]) + ")");
+      }
+    }
+  }
+  *iters = it;
+  *rr_out = rr;
+  return HX_OK;
+}
+
+// Lanczos estimate of lambda_max(D^-1 A): `steps` Jacobi-PCG iterations from a seeded random right-hand
+// side; the CG coefficients give the Lanczos tridiagonal T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+// T_{j,j+1} = sqrt(beta_j)/alpha_j, whose largest eigenvalue approaches lambda_max from below.
+hx_status lanczos_lambda_max(Ctx &c, const Vecs<double> &v, int steps, double *lmax) {
+  std::vector<double> h(c.n);
+  std::mt19937_64 rng(12345);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  for (auto &t : h) t = U(rng);
+  HX_HIP(hipMemcpyAsync(v.r, h.data(), sizeof(double) * c.n, hipMemcpyHostToDevice, c.s));
+  if (c.nc == 1) LAUNCH_V((k_maskset<1>), c.n, c.op.mesh->freemask.ptr, v.r);
+  else LAUNCH_V((k_maskset<3>), c.n, c.op.mesh->freemask.ptr, v.r);
+  HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, c.s));
+  LAUNCH_V((k_jacobi<double>), c.n, v.dinv, v.r, v.z, c.part0);
+  FINAL(c.part0, (const double *)nullptr, FIN_RZ, 0);
+  HX_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * c.n, hipMemcpyDeviceToDevice, c.s));
+  HX_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * c.n, c.s));
+  std::vector<double> al, be;
+  for (int it = 0; it < steps; ++it) {
+    if (hx_status st = apply_T(c, v.p, v.w, HX_FP64)) return st;
+    LAUNCH_V((k_dot<double>), c.n, v.p, v.w, c.part0);
+    FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
+    if (c.nc == 1) LAUNCH_V((k_update<double, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1);
+    else LAUNCH_V((k_update<double, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1);
+    FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
+    LAUNCH_V((k_pupd<double>), c.n, c.S, v.z, v.p);
+    if (hx_status e = read_scalars(c)) return e;
+    if (c.hS[S_FLAG] != 0.0 || !(c.hS[S_ALPHA] > 0)) break;
+    al.push_back(c.hS[S_ALPHA]);
+    be.push_back(c.hS[S_BETA]);
+    if (c.hS[S_RR] == 0.0) break;
+  }
+  if (al.empty()) return fail(HX_EBREAKDOWN, "Lanczos estimate failed (zero right-hand side or breakdown)");
+  const int m = (int)al.size();
+  std::vector<double> d(m), e(m > 1 ? m - 1 : 0);
+  for (int j = 0; j < m; ++j) {
+    d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < m) e[j] = std::sqrt(be[j]) / al[j];
+  }
+  *lmax = tridiag_max_eig(d, e);
+  return HX_OK;
+}
+
+template <typename T>
+hx_status carve(DevBuf<T> &buf, int64_t n, Vecs<T> &v) {
+  if (buf.count < (size_t)(8 * n)) HX_HIP(buf.alloc((size_t)8 * n));
+  T *b = buf.ptr;
+  v = Vecs<T>{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n, b + 7 * n};
+  return HX_OK;
+}
+
+struct PinnedHost {
+  double *p = nullptr;
+  ~PinnedHost() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+}  // namespace
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
+  if (!o) return;
+  o->mode = HX_SOLVE_FP64;
+  o->precond = HX_PC_JACOBI;
+  o->rtol = 1e-8;
+  o->maxit = 10000;
+  o->check_every = 10;
+  o->use_x0 = 0;
+  o->cheb_degree = 4;
+  o->cheb_ratio = 30.0;
+  o->cheb_prec = HX_FP32;
+  o->lanczos_steps = 20;
+  o->inner_rtol = 1e-4;
+  o->inner_maxit = 200;
+  o->inner_qdata = HX_FP64;
+}
+
+extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
+                                  hx_solve_info *info, hx_stream stream) {
+  if (!op || !b || !x || !opts || !info) return fail(HX_EINVAL, "null argument");
+  const hx_solve_opts &o = *opts;
+  if (o.mode != HX_SOLVE_FP64 && o.mode != HX_SOLVE_IR) return fail(HX_EINVAL, "mode must be HX_SOLVE_FP64 or HX_SOLVE_IR");
+  if (o.precond < HX_PC_NONE || o.precond > HX_PC_CHEBYSHEV) return fail(HX_EINVAL, "precond out of range");
+  if (!(o.rtol > 0) || o.maxit < 1 || o.check_every < 1) return fail(HX_EINVAL, "need rtol > 0, maxit >= 1, check_every >= 1");
+  const bool cheb = o.precond == HX_PC_CHEBYSHEV;
+  if (cheb && (o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) || o.lanczos_steps < 2))
+    return fail(HX_EINVAL, "Chebyshev needs cheb_degree >= 1, cheb_ratio > 1, lanczos_steps >= 2");
+  if (cheb && o.cheb_prec != HX_FP64 && o.cheb_prec != HX_FP32 && o.cheb_prec != HX_BF16)
+    return fail(HX_EINVAL, "cheb_prec must be HX_FP64, HX_FP32 or HX_BF16");
+  if (o.mode == HX_SOLVE_IR && (!(o.inner_rtol > 0 && o.inner_rtol < 1) || o.inner_maxit < 1))
+    return fail(HX_EINVAL, "IR needs 0 < inner_rtol < 1 and inner_maxit >= 1");
+  if (o.mode == HX_SOLVE_IR && o.inner_qdata != HX_FP64 && o.inner_qdata != HX_FP32)
+    return fail(HX_EINVAL, "inner_qdata must be HX_FP64 or HX_FP32");
+  if (o.mode == HX_SOLVE_IR && cheb && o.cheb_prec == HX_FP64)
+    return fail(HX_EINVAL, "the IR inner solve runs in FP32: cheb_prec must be HX_FP32 or HX_BF16");
+  if (cheb && o.cheb_prec == HX_BF16 && (op->kind != HX_DIFFUSION || op->ncomp != 1))
+    return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
+  *info = hx_solve_info{};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = op->mesh->nnodes * op->ncomp;
+  const int NC = op->ncomp;
+  const auto t_setup0 = std::chrono::steady_clock::now();
+
+  if (op->red.count < (size_t)(2 * kVecBlocks + S_NSCAL)) HX_HIP(op->red.alloc(2 * kVecBlocks + S_NSCAL));
+  PinnedHost hs;
+  HX_HIP(hipHostMalloc(reinterpret_cast<void **>(&hs.p), sizeof(double) * S_NSCAL));
+  Ctx c{*op, s, n, NC, op->red.ptr, op->red.ptr + kVecBlocks, op->red.ptr + 2 * kVecBlocks, hs.p, 0};
+
+  Vecs<double> v;
+  if (hx_status st = carve(op->work, n, v)) return st;
+  const bool need_diag = o.precond != HX_PC_NONE;
+  if (need_diag && !op->diag_valid) {
+    if (op->diag.count < (size_t)n) HX_HIP(op->diag.alloc(n));
+    if (hx_status st = hx_op_diagonal(op, op->diag.ptr, stream)) return st;
+    op->diag_valid = true;
+  }
+  const double *dg = need_diag ? op->diag.ptr : nullptr;
+  if (NC == 1) LAUNCH_V((k_dinv<double, 1>), n, dg, op->mesh->freemask.ptr, v.dinv);
+  else LAUNCH_V((k_dinv<double, 3>), n, dg, op->mesh->freemask.ptr, v.dinv);
+  HX_HIP(hipGetLastError());
+
+  const bool use32 = o.mode == HX_SOLVE_IR || (cheb && o.cheb_prec != HX_FP64);
+  Vecs<float> v32{};
+  if (use32) {
+    if (hx_status st = carve(op->work32, n, v32)) return st;
+    LAUNCH_V((k_convert<double, float>), n, 1.0, v.dinv, v32.dinv);
+    const bool q32 = (o.mode == HX_SOLVE_IR && o.inner_qdata == HX_FP32) || (cheb && o.cheb_prec == HX_FP32);
+    if (q32)
+      if (hx_status st = make_qdata32(*op, s)) return st;
+    HX_HIP(hipGetLastError());
+  }
+
+  Cheb ch;
+  ch.degree = o.cheb_degree;
+  if (cheb) {
+    double lmax = 0;
+    if (hx_status st = lanczos_lambda_max(c, v, o.lanczos_steps, &lmax)) return st;
+    ch.lam_hi = 1.1 * lmax;
+    ch.lam_lo = ch.lam_hi / o.cheb_ratio;
+    info->lam_max = lmax;
+  }
+  HX_HIP(hipStreamSynchronize(s));
+  const auto t0 = std::chrono::steady_clock::now();
+  info->setup_seconds = std::chrono::duration<double>(t0 - t_setup0).count();
+  c.applies = 0;
+
+  if (o.use_x0) {
+    if (NC == 1) LAUNCH_V((k_maskset<1>), n, op->mesh->freemask.ptr, x);
+    else LAUNCH_V((k_maskset<3>), n, op->mesh->freemask.ptr, x);
+  } else {
+    HX_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  }
+  // ||b|| over the free nodes
+  if (NC == 1) LAUNCH_V((k_resid<double, double, 1>), n, 1.0, b, (const double *)nullptr, op->mesh->freemask.ptr, v.r, c.part1);
+  else LAUNCH_V((k_resid<double, double, 3>), n, 1.0, b, (const double *)nullptr, op->mesh->freemask.ptr, v.r, c.part1);
+  FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_BB);
+  if (hx_status st = read_scalars(c)) return st;
+  const double bb = c.hS[S_BB];
+  if (!std::isfinite(bb)) return fail(HX_EBREAKDOWN, "right-hand side is not finite");
+  if (bb == 0.0) {
+    HX_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    HX_HIP(hipStreamSynchronize(s));
+    info->solve_seconds = 0.0;
+    return HX_OK;
+  }
+  const double bn = std::sqrt(bb);
+
+  // v.r = m (b - A x) in FP64; returns r'r
+  auto residual = [&](double *rr_out) -> hx_status {
+    if (hx_status st = apply_T(c, x, v.w, HX_FP64)) return st;
+    if (NC == 1) LAUNCH_V((k_resid<double, double, 1>), n, 1.0, b, v.w, op->mesh->freemask.ptr, v.r, c.part1);
+    else LAUNCH_V((k_resid<double, double, 3>), n, 1.0, b, v.w, op->mesh->freemask.ptr, v.r, c.part1);
+    HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, s));
+    FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_RR);
+    if (hx_status st = read_scalars(c)) return st;
+    *rr_out = c.hS[S_RR];
+    return HX_OK;
+  };
+
+  hx_status result = HX_OK;
+  double rr = 0.0;
+  if (hx_status st = residual(&rr)) return st;
+  if (o.mode == HX_SOLVE_FP64) {
+    // solve A d = r0 in FP64 for the correction d (v.x), then x += d
+    PrecFn<double> pc64 = [&](const double *r, double *z) -> hx_status {
+      return cheb_apply<double>(c, ch, v, r, z, HX_FP64);
+    };
+    PrecFn<double> pc32 = [&](const double *r, double *z) -> hx_status {
+      LAUNCH_V((k_convert<double, float>), n, 1.0, r, v32.r);
+      if (hx_status st = cheb_apply<float>(c, ch, v32, v32.r, v32.z, o.cheb_prec)) return st;
+      LAUNCH_V((k_convert<float, double>), n, 1.0, v32.z, z);
+      return HX_OK;
+    };
+    const PrecFn<double> *pc = nullptr;
+    if (cheb) pc = (o.cheb_prec == HX_FP64) ? &pc64 : &pc32;
+    int it = 0;
+    double rre = 0;
+    result = pcg_core<double>(c, v, pc, HX_FP64, rr, o.rtol * o.rtol * bb, o.maxit, o.check_every, &it, &rre);
+    LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
+    info->iterations = it;
+    info->rel_residual = std::sqrt(rre) / bn;
+  } else {
+    // iterative refinement: FP64 residual, FP32 inner PCG on r / ||r||, FP64 update x += ||r|| d
+    int outer = 0, inner_total = 0;
+    const int inner_prec = cheb ? o.cheb_prec : o.inner_qdata;
+    const int cg_prec = (o.inner_qdata == HX_FP32) ? HX_FP32 : HX_FP64;  // FP32 vectors, qdata precision
+    PrecFn<float> pcc = [&](const float *r, float *z) -> hx_status {
+      return cheb_apply<float>(c, ch, v32, r, z, inner_prec);
+    };
+    while (rr > o.rtol * o.rtol * bb) {
+      if (!std::isfinite(rr)) {
+        result = fail(HX_EBREAKDOWN, "non-finite residual in refinement");
+        break;
+      }
+      if (outer >= o.maxit) {
+        result = fail(HX_ENOCONV, "iterative refinement reached maxit outer steps");
+        break;
+      }
+      const double rn = std::sqrt(rr);
+      LAUNCH_V((k_convert<double, float>), n, 1.0 / rn, v.r, v32.r);
+      int it = 0;
+      double rri = 0;
+      // inner r'r starts at ~1 (the residual is normalised)
+      hx_status st = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, cg_prec, 1.0, o.inner_rtol * o.inner_rtol,
+                                     o.inner_maxit, std::min(o.check_every, o.inner_maxit), &it, &rri);
+      if (st == HX_EBREAKDOWN && it > 1) st = HX_OK;  // keep the partial correction; the FP64 residual judges it
+      if (st) return st;
+      inner_total += it;
+      LAUNCH_V((k_axpy<float>), n, rn, v32.x, x);
+      HX_HIP(hipGetLastError());
+      ++outer;
+      if (hx_status st2 = residual(&rr)) return st2;
+    }
+    info->iterations = inner_total;
+    info->outer_iterations = outer;
+    info->rel_residual = std::sqrt(rr) / bn;
+  }
+  HX_HIP(hipStreamSynchronize(s));
+  const auto t1 = std::chrono::steady_clock::now();
+  info->solve_seconds = std::chrono::duration<double>(t1 - t0).count();
+  info->operator_applies = c.applies;
+  double rr_true = 0;
+  if (hx_status st = residual(&rr_true)) return st;
+  info->true_rel_residual = std::sqrt(rr_true) / bn;
+  if (result == HX_OK && o.mode == HX_SOLVE_FP64 && info->rel_residual > o.rtol)
+    result = fail(HX_ENOCONV, "PCG reached maxit without meeting rtol");
+  return result;
+}

@@ -1,0 +1,113 @@
+"""GPU PCG solves against the oracle: iteration counts, residuals, and solutions vs a direct solve."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fem, solvers  # noqa: E402
+from paper_2109_04996_amd import hexpa as hx  # noqa: E402
+from paper_2109_04996_amd.inputs import lattice_mesh  # noqa: E402
+from paper_2109_04996_amd.problem import Problem  # noqa: E402
+
+
+def _sine(X):
+    return np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+
+
+def _setup(N, p, q, rule, ncomp=1, warp="A", seed=0):
+    """GPU operator + GPU RHS b = B f^ (mass with q = p+2 Gauss), and the oracle's matrices."""
+    print(f"\n[case] solve N={N} p={p} q={q} rule={rule} ncomp={ncomp} warp={warp}", flush=True)
+    mesh = lattice_mesh(N, p, warp=warp, shuffle_seed=seed)
+    pr = Problem(N, p, q, rule, "diffusion", ncomp=ncomp, mesh=mesh)
+    mass = Problem(N, p, p + 2, "gauss", "mass", ncomp=ncomp, mesh=mesh)
+    s = np.array([1.0, -1.0, 0.5])[:ncomp]
+    f = (3 * np.pi ** 2 * _sine(pr.xyz))[:, None] * s[None, :]
+    b = mass.apply(pr.to_dev(f.ravel()))
+    mass.close()
+    A = fem.assemble(mesh, p, q, rule, "diffusion")
+    B = fem.assemble(mesh, p, p + 2, "gauss", "mass")
+    X = fem.node_coordinates(mesh, p)
+    fo = ((3 * np.pi ** 2 * _sine(X))[:, None] * s[None, :]).ravel()
+    Ak = solvers.expand(A, ncomp)
+    bo = solvers.expand(B, ncomp) @ fo
+    free = solvers.free_mask(mesh["boundary"], ncomp)
+    return mesh, pr, b, Ak, bo, free
+
+
+@pytest.mark.parametrize("N,p,q,rule", [(4, 3, 5, "gauss"), (4, 4, 5, "gll"), (3, 7, 8, "gll")])
+def test_jacobi_pcg_matches_oracle(N, p, q, rule):
+    mesh, pr, b, A, bo, free = _setup(N, p, q, rule)
+    with pr:
+        np.testing.assert_allclose(b.cpu().numpy(), bo, rtol=1e-12, atol=1e-14 * np.abs(bo).max())
+        x, info = pr.solve(b, rtol=1e-8, check_every=1)
+        xo, ito, reso = solvers.jacobi_pcg(A, bo, free, tol=1e-8)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        assert abs(info["iterations"] - ito) <= 2, (info["iterations"], ito)
+        xd = solvers.direct_solve(A, bo, free)
+        x = x.cpu().numpy()
+        assert np.all(x[~free] == 0)
+        # both stop at a 1e-8 residual: their solutions agree to the oracle's own distance from x*
+        tol = 3 * np.linalg.norm(xo - xd) + 1e-12 * np.linalg.norm(xd)
+        assert np.linalg.norm(x - xd) <= tol
+        # tight solve: agree with the direct solve
+        x2, info2 = pr.solve(b, rtol=1e-13, check_every=5)
+        assert np.linalg.norm(x2.cpu().numpy() - xd) <= 1e-10 * np.linalg.norm(xd), info2
+
+
+def test_vector_pcg_matches_oracle():
+    mesh, pr, b, A, bo, free = _setup(3, 5, 7, "gauss", ncomp=3)
+    with pr:
+        x, info = pr.solve(b, rtol=1e-12)
+        xd = solvers.direct_solve(A, bo, free)
+        assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-9 * np.linalg.norm(xd)
+        for c, sc in enumerate([1.0, -1.0, 0.5]):
+            xc = x.cpu().numpy()[c::3]
+            np.testing.assert_allclose(xc, sc * x.cpu().numpy()[0::3], rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("cheb_prec", [hx.HX_FP64, hx.HX_FP32])
+def test_chebyshev_pcg(cheb_prec):
+    mesh, pr, b, A, bo, free = _setup(4, 4, 6, "gauss", warp="B")
+    with pr:
+        xj, ij = pr.solve(b, rtol=1e-10)
+        x, info = pr.solve(b, rtol=1e-10, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=cheb_prec)
+        assert info["true_rel_residual"] <= 1.05e-10
+        assert info["iterations"] < ij["iterations"]
+        lmax = solvers.jacobi_lambda_max(A, free)
+        assert 0.8 * lmax <= info["lam_max"] <= 1.0001 * lmax, (info["lam_max"], lmax)
+        xd = solvers.direct_solve(A, bo, free)
+        assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("precond,qd", [(hx.HX_PC_JACOBI, hx.HX_FP64), (hx.HX_PC_JACOBI, hx.HX_FP32),
+                                        (hx.HX_PC_CHEBYSHEV, hx.HX_FP32)])
+def test_iterative_refinement(precond, qd):
+    mesh, pr, b, A, bo, free = _setup(4, 5, 7, "gauss", warp="B")
+    with pr:
+        x, info = pr.solve(b, mode=hx.HX_SOLVE_IR, precond=precond, inner_qdata=qd, rtol=1e-8)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        assert info["outer_iterations"] >= 2
+        xd = solvers.direct_solve(A, bo, free)
+        xo, _, _ = solvers.jacobi_pcg(A, bo, free, tol=1e-8)
+        # error of the mixed solve is of the size of the plain FP64 solve's at the same residual
+        assert np.linalg.norm(x.cpu().numpy() - xd) <= 10 * np.linalg.norm(xo - xd) + 1e-12
+
+
+def test_failures_reported():
+    mesh, pr, b, A, bo, free = _setup(3, 3, 5, "gauss")
+    with pr:
+        x, info = pr.solve(b, maxit=2, check_every=1, raise_on_error=False)
+        assert info["status"] == "HX_ENOCONV" and info["iterations"] == 2
+        bn = b.clone()
+        bn[int(np.flatnonzero(free)[3])] = float("nan")
+        x, info = pr.solve(bn, raise_on_error=False)
+        assert info["status"] == "HX_EBREAKDOWN"
+        # warm start from the converged solution: done at once
+        x0, _ = pr.solve(b, rtol=1e-10)
+        x1, info = pr.solve(b, x=x0.clone(), use_x0=1, rtol=1e-9, check_every=1)
+        assert info["iterations"] <= 1
+        zero = torch.zeros_like(b)
+        x2, info = pr.solve(zero)
+        assert torch.count_nonzero(x2) == 0
