@@ -1,0 +1,226 @@
+"""Throughput of the fused BP5 diffusion apply (p=7, q=8 GLL-collocated, FP64) on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 48] [--p 7] [--no-solves] [--no-cpu-baseline]
+
+A step is one operator apply y = A x over the whole L-vector (all element colors), inputs resident in
+HBM. Prints one JSON line with the metric, the roofline object of the apply kernel, the oracle CPU
+baseline, and time-to-1e-8 PCG solves on the same mesh.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "GDOF/s diffusion apply p=7; time-to-1e-8 PCG solve, plain FP64 vs mixed/learned"
+COUNTERS = os.path.join(ROOT, "profiles", "bp5_p7_n48_counters.json")
+KERNEL_SOURCES = ["paper_2109_04996_amd/csrc/apply_kernel.h", "paper_2109_04996_amd/csrc/apply_launch.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, E: int, P: int, Q: int, ncq: int = 6, ncomp: int = 1) -> dict:
+    """Bytes the method must move per apply: read x and write y once (8 B each per DOF), the stored
+    pointwise data (ncq FP64 values per point), the element restriction (one int32 per element node)."""
+    xy = 16 * n * ncomp
+    qd = 8 * ncq * Q ** 3 * E
+    ix = 4 * P ** 3 * E
+    return dict(total=xy + qd + ix, xy=xy, qdata=qd, index=ix, per_element=(xy + qd + ix) / E)
+
+
+def time_applies(pr, x, y, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        pr.apply(x, y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        pr.apply(x, y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    # per-apply distribution (events around each apply, separately)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * min(steps, 50))]
+    for i in range(0, len(evs), 2):
+        evs[i].record(stream)
+        pr.apply(x, y)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(0, len(evs), 2))
+    return total_ms, wall, per
+
+
+def copy_probe(nbytes=4 << 30):
+    """Device-to-device copy bandwidth (read + write) of a large buffer: the memcpy probe."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def solves(pr, mass_pr, maxit=20000):
+    """Time-to-1e-8 for plain FP64 Jacobi-PCG and the mixed-precision forms, same RHS b = B f^."""
+    import numpy as np
+    import torch
+
+    from paper_2109_04996_amd import hexpa as hx
+    X = pr.xyz
+    f = 3 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+    b = mass_pr.apply(pr.to_dev(f))
+    out = {}
+    forms = {
+        "fp64_jacobi": dict(),
+        "fp64_cg_cheb4_fp32op": dict(precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32),
+        "ir_fp32_jacobi": dict(mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_JACOBI, inner_qdata=hx.HX_FP32),
+        "ir_fp32_cheb4": dict(mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32,
+                              inner_qdata=hx.HX_FP32),
+    }
+    ref = None
+    for name, o in forms.items():
+        print(f"[bench] solve {name}", file=sys.stderr, flush=True)
+        x = pr.zeros()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = pr.solve(b, x=x, rtol=1e-8, maxit=maxit, check_every=25, raise_on_error=False, **o)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        xs = x.double()
+        if ref is None:
+            ref = xs.clone()
+        out[name] = dict(status=info["status"], iterations=info["iterations"],
+                         outer=info["outer_iterations"], applies=info["operator_applies"],
+                         seconds=round(info["solve_seconds"], 4), setup_seconds=round(info["setup_seconds"], 4),
+                         wall_seconds=round(wall, 4), true_rel_residual=info["true_rel_residual"],
+                         rel_diff_vs_fp64=float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)))
+    return out
+
+
+def cpu_baseline(p: int, budget_s: float = 20.0):
+    """The oracle (scipy CSR SpMV of the assembled matrix) on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import fem
+    from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
+    N = 6
+    t0 = time.perf_counter()
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    A = fem.assemble(mesh, p, p + 1, "gll", "diffusion")
+    t_asm = time.perf_counter() - t0
+    x = uniform_vector(mesh["nnodes"], 1)
+    reps, t = 0, 0.0
+    while t < budget_s * 0.5 and reps < 200:
+        t1 = time.perf_counter()
+        A @ x
+        t += time.perf_counter() - t1
+        reps += 1
+    n = mesh["nnodes"]
+    return dict(value=round(n * reps / t / 1e9, 5), unit="GDOF/s", cores=1, kind="oracle",
+                sample=f"oracle scipy CSR SpMV (single thread) of the assembled BP5 p={p} q={p + 1} GLL matrix, "
+                       f"mesh A {N}^3 elements, {n} DOFs, nnz {A.nnz}, {reps} applies in {t:.2f} s; "
+                       f"assembly {t_asm:.1f} s excluded")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--N", type=int, default=48)
+    ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build measures the single-GPU "
+              "path, and multi-GPU sharding is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
+    from paper_2109_04996_amd.problem import Problem
+
+    hx.load()
+    torch.cuda.set_device(0)
+    N, p = a.N, a.p
+    P = Q = p + 1
+    print(f"[bench] building BP5 mesh N={N} p={p}", file=sys.stderr, flush=True)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    pr = Problem(N, p, Q, "gll", "diffusion", mesh=mesh)
+    n, E = mesh["nnodes"], mesh["nelem"]
+    x = pr.to_dev(uniform_vector(n, 1))
+    y = pr.zeros()
+    print(f"[bench] n={n} E={E} colors={pr.stats['ncolors']}; timing {a.steps} applies", file=sys.stderr, flush=True)
+    total_ms, wall, per = time_applies(pr, x, y, a.steps, a.warmup)
+    ms = total_ms / a.steps
+    gdofs = n / (ms * 1e-3) / 1e9
+    ab = algorithmic_bytes(n, E, P, Q)
+    ncol = pr.stats["ncolors"]
+    achieved = ab["total"] / (ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS):
+        c = json.load(open(COUNTERS))
+        if c.get("kernel_hash") == kernel_hash() and c.get("workload") == f"bp5_p{p}_n{N}":
+            traffic = c.get("hbm_bytes_per_launch")
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="hx::k_apply<8,8,MODE_COLLOC,1,double,double,false>",
+                launches_per_apply=ncol, algorithmic_bytes_per_launch=round(ab["total"] / ncol),
+                avg_launch_us=round(1e3 * ms / ncol, 2), algorithmic_bytes_per_dof=round(ab["total"] / n, 2),
+                kernel_hash=kernel_hash())
+    out = dict(metric=METRIC, value=round(gdofs, 3), unit="GDOF/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload=f"BP5 scalar diffusion apply, p={p}, q={Q} GLL-collocated, FP64, "
+                                    f"warped unit-cube mesh A {N}^3 elements shuffled (seed 0), {n} DOFs, "
+                                    f"x ~ U[-1,1] (seed 1)",
+                           N=N, p=p, q=Q, dofs=n, elements=E, colors=ncol),
+               p10_ms=round(per[len(per) // 10], 4), p90_ms=round(per[(9 * len(per)) // 10], 4),
+               roofline=roof)
+    if a.copy_probe:
+        out["copy_probe_GBs"] = round(copy_probe(), 1)
+    if not a.no_solves:
+        mass_pr = Problem(N, p, p + 2, "gauss", "mass", mesh=mesh)
+        out["solves"] = dict(workload=f"BP5 p={p} N={N} Dirichlet, b = B f^, f = 3 pi^2 sin sin sin, rtol 1e-8",
+                             **solves(pr, mass_pr))
+        mass_pr.close()
+    pr.close()
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

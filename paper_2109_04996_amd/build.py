@@ -60,8 +60,14 @@ def _compile(src: str) -> tuple[str, float, str]:
     return obj, time.time() - t0, warn
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, out: str | None = None, defines=(),
+          build_dir: str | None = None) -> str:
+    """Compile every source and link ``out`` (default: the in-tree libhexpa.so)."""
+    global BUILD
+    if build_dir:
+        BUILD = build_dir
     os.makedirs(BUILD, exist_ok=True)
+    COMMON.extend(f"-D{d}" for d in defines if f"-D{d}" not in COMMON)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     t0 = time.time()
@@ -73,15 +79,16 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
                 print(f"  compiled {os.path.basename(obj)} in {dt:.1f}s", flush=True)
             if warn and verbose:
                 print(warn, flush=True)
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f}s", flush=True)
+    return lib
 
 
 def main():

@@ -113,7 +113,22 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
   // device tables: collocated D [P][P]; otherwise interp [Q][P] then the q-point derivative [Q][Q]
   std::vector<double> tab;
   if (op->colloc) {
+    // D [P][P], then its even-odd coefficients E [h][h+odd], O [h][h], M [h] (odd P)
     tab = op->b.grad;
+    const int P = op->P, h = P / 2, odd = P & 1, he = h + odd;
+    const std::vector<double> &D = op->b.grad;
+    std::vector<double> E(h * he), O(h * h), M(odd * h);
+    for (int i = 0; i < h; ++i) {
+      for (int l = 0; l < h; ++l) {
+        E[i * he + l] = 0.5 * (D[i * P + l] + D[i * P + P - 1 - l]);
+        O[i * h + l] = 0.5 * (D[i * P + l] - D[i * P + P - 1 - l]);
+      }
+      if (odd) E[i * he + h] = D[i * P + h];
+    }
+    for (int l = 0; l < odd * h; ++l) M[l] = D[h * P + l];
+    tab.insert(tab.end(), E.begin(), E.end());
+    tab.insert(tab.end(), O.begin(), O.end());
+    tab.insert(tab.end(), M.begin(), M.end());
   } else {
     tab = op->b.interp;
     tab.insert(tab.end(), op->b.colloc.begin(), op->b.colloc.end());

@@ -22,9 +22,10 @@
 //                to the q^3 points with the 1D table, differentiate there with
 //                the collocated derivative matrix of the q points.
 //   MODE_MASS    mass (BP1/BP2): interpolate, scale by w detJ, project back.
-// Pointwise data (qdata) per element and point, structure-of-arrays inside an
-// element: mass w*detJ; diffusion the 6 entries G11 G12 G13 G22 G23 G33 of
-// w*kappa*detJ*J^-1 J^-T.
+// Pointwise data (qdata) per element: mass w*detJ; diffusion the 6 entries
+// G11 G12 G13 G22 G23 G33 of w*kappa*detJ*J^-1 J^-T. Layout [e][qc][m][qb][qa]:
+// plane by plane along r3, the components of a plane next to each other, so a
+// wavefront reads each component of a plane as one contiguous run.
 //
 // Scatter: no atomics. Elements of one launch never share a node (coloring);
 // bit k of own[e][j][i] says element e is the first to write node (i,j,k),
@@ -125,9 +126,9 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
             us += tD[b * P + l] * A[k * P2 + l * P + a];
             ut += tD[k * P + l] * u[l];
           }
-          const TQ *g = qe + k * Q2;
-          const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q3), g2 = ld_q<TQ, T>(g + 2 * Q3);
-          const T g3 = ld_q<TQ, T>(g + 3 * Q3), g4 = ld_q<TQ, T>(g + 4 * Q3), g5 = ld_q<TQ, T>(g + 5 * Q3);
+          const TQ *g = qe + k * 6 * Q2;
+          const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q2), g2 = ld_q<TQ, T>(g + 2 * Q2);
+          const T g3 = ld_q<TQ, T>(g + 3 * Q2), g4 = ld_q<TQ, T>(g + 4 * Q2), g5 = ld_q<TQ, T>(g + 5 * Q2);
           B[k * P2 + b * P + a] = g0 * ur + g1 * us + g2 * ut;
           C[k * P2 + b * P + a] = g1 * ur + g3 * us + g4 * ut;
           const T vt = g2 * ur + g4 * us + g5 * ut;
@@ -205,9 +206,9 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
               us += tD[b * Q + l] * C[cq * Q2 + l * Q + a];
               ut += tD[cq * Q + l] * uq[l];
             }
-            const TQ *g = qe + cq * Q2;
-            const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q3), g2 = ld_q<TQ, T>(g + 2 * Q3);
-            const T g3 = ld_q<TQ, T>(g + 3 * Q3), g4 = ld_q<TQ, T>(g + 4 * Q3), g5 = ld_q<TQ, T>(g + 5 * Q3);
+            const TQ *g = qe + cq * 6 * Q2;
+            const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q2), g2 = ld_q<TQ, T>(g + 2 * Q2);
+            const T g3 = ld_q<TQ, T>(g + 3 * Q2), g4 = ld_q<TQ, T>(g + 4 * Q2), g5 = ld_q<TQ, T>(g + 5 * Q2);
             A[cq * Q2 + b * Q + a] = g0 * ur + g1 * us + g2 * ut;
             B[cq * Q2 + b * Q + a] = g1 * ur + g3 * us + g4 * ut;
             const T vt = g2 * ur + g4 * us + g5 * ut;
@@ -267,14 +268,11 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
 #pragma unroll
         for (int k = 0; k < P; ++k) ye[k * P2] = yv[k];
       } else {
+        T old[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-          T *dst = y + (int64_t)nid[k] * NC + c;
-          if (ob & (1u << k))
-            *dst = yv[k];
-          else
-            *dst += yv[k];
-        }
+        for (int k = 0; k < P; ++k) old[k] = (ob & (1u << k)) ? T(0) : y[(int64_t)nid[k] * NC + c];
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + yv[k];
       }
     }
     if constexpr (NC > 1) __syncthreads();

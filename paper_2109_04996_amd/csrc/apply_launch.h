@@ -2,12 +2,28 @@
 #pragma once
 
 #include "apply_kernel.h"
+#include "colloc_kernel.h"
 #include "hx_internal.h"
 
 namespace hx {
 
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
+  if constexpr (MODE == MODE_COLLOC && P <= 8) {
+    // line-per-thread collocated kernel
+    using CF = CollocCfg<P>;
+    const hx_mesh_s &m = *op.mesh;
+    for (int c = 0; c < m.ncolors; ++c) {
+      const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
+      if (e1 <= e0) continue;
+      const int64_t nb = (e1 - e0 + CF::EPB - 1) / CF::EPB;
+      hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s, a.idx, a.own,
+                         qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_colloc launch");
+    return HX_OK;
+  }
   constexpr int EPB = EpbOf<Q>::v;
   const hx_mesh_s &m = *op.mesh;
   for (int c = 0; c < m.ncolors; ++c) {

@@ -56,6 +56,13 @@ void gauss_nodes_weights(int q, std::vector<double> &x, std::vector<double> &w) 
     x[i] = t;
     w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
   }
+  // exact symmetry about 0 (the even-odd kernels rely on it)
+  for (int i = 0; i < q / 2; ++i) {
+    const double s = 0.5 * (x[q - 1 - i] - x[i]), ws = 0.5 * (w[i] + w[q - 1 - i]);
+    x[i] = -s;
+    x[q - 1 - i] = s;
+    w[i] = w[q - 1 - i] = ws;
+  }
   if (q % 2 == 1) x[q / 2] = 0.0;
 }
 
@@ -78,6 +85,11 @@ void gll_nodes_weights(int p, std::vector<double> &x, std::vector<double> &w) {
     x[i] = t;
   }
   if (p % 2 == 0) x[p / 2] = 0.0;
+  for (int i = 1; i < n / 2; ++i) {
+    const double s = 0.5 * (x[n - 1 - i] - x[i]);
+    x[i] = -s;
+    x[n - 1 - i] = s;
+  }
   for (int i = 0; i < n; ++i) {
     double pn, pm;
     legendre(p, x[i], pn, pm);

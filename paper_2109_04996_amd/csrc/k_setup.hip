@@ -7,7 +7,7 @@
 // and stored (partial assembly):
 //   mass       w detJ
 //   diffusion  w kappa detJ J^-1 J^-T = w kappa adj(J) adj(J)^T / detJ
-// stored as 6 symmetric entries per point, structure-of-arrays per element.
+// stored as 6 symmetric entries per point, layout [e][qc][m][qb][qa] (plane by plane).
 // Miniapps section (Nekbone's diagonal preconditioner): the diagonal of the
 // assembled operator is sum_e G_e^T diag(B^T D B), computed here point by
 // point from the 1D tables without forming element matrices.
@@ -87,7 +87,9 @@ __global__ void __launch_bounds__(kSetupThreads)
     const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
     if (!(det > 0.0)) *bad = 1;
     const double w = sw[qa] * sw[qb] * sw[qc];
-    double *out = qd + e * (int64_t)(ncq * Q3) + pt;
+    // layout [e][qc][m][qb][qa]
+    double *out = qd + e * (int64_t)(ncq * Q3) + (int64_t)qc * ncq * Q * Q + qb * Q + qa;
+    const int Q2 = Q * Q;
     if (kind == HX_MASS) {
       out[0] = w * det;
     } else {
@@ -106,12 +108,12 @@ __global__ void __launch_bounds__(kSetupThreads)
       for (int r = 0; r < 3; ++r)
         for (int c = r; c < 3; ++c)
           G[r][c] = s * (adj[r][0] * adj[c][0] + adj[r][1] * adj[c][1] + adj[r][2] * adj[c][2]);
-      out[0 * Q3] = G[0][0];
-      out[1 * Q3] = G[0][1];
-      out[2 * Q3] = G[0][2];
-      out[3 * Q3] = G[1][1];
-      out[4 * Q3] = G[1][2];
-      out[5 * Q3] = G[2][2];
+      out[0 * Q2] = G[0][0];
+      out[1 * Q2] = G[0][1];
+      out[2 * Q2] = G[0][2];
+      out[3 * Q2] = G[1][1];
+      out[4 * Q2] = G[1][2];
+      out[5 * Q2] = G[2][2];
     }
   }
 }
@@ -141,14 +143,16 @@ __global__ void __launch_bounds__(kSetupThreads)
         const double Ij = sI[qb * P + j], Gj = sG[qb * P + j];
         for (int qa = 0; qa < Q; ++qa) {
           const double Ii = sI[qa * P + i], Gi = sG[qa * P + i];
-          const int pt = qa + Q * (qb + Q * qc);
+          // layout [qc][m][qb][qa]
+          const double *g = qe + (qc * ncq) * Q * Q + qb * Q + qa;
+          const int Q2 = Q * Q;
           if (kind == HX_MASS) {
             const double v = Ii * Ij * Ik;
-            s += qe[pt] * v * v;
+            s += g[0] * v * v;
           } else {
             const double d0 = Gi * Ij * Ik, d1 = Ii * Gj * Ik, d2 = Ii * Ij * Gk;
-            s += qe[pt] * d0 * d0 + qe[3 * Q3 + pt] * d1 * d1 + qe[5 * Q3 + pt] * d2 * d2 +
-                 2.0 * (qe[Q3 + pt] * d0 * d1 + qe[2 * Q3 + pt] * d0 * d2 + qe[4 * Q3 + pt] * d1 * d2);
+            s += g[0] * d0 * d0 + g[3 * Q2] * d1 * d1 + g[5 * Q2] * d2 * d2 +
+                 2.0 * (g[Q2] * d0 * d1 + g[2 * Q2] * d0 * d2 + g[4 * Q2] * d1 * d2);
           }
         }
       }

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libhexpa.so")
+LIB_PATH = os.environ.get("HEXPA_LIB") or os.path.join(_PKG, "libhexpa.so")
 
 HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOWN, HX_EHIP, HX_ENOMEM = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
