@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "GDOF/s diffusion apply p=7; time-to-1e-8 PCG solve, plain FP64 vs mixed/learned"
 COUNTERS = os.path.join(ROOT, "profiles", "bp5_p7_n48_counters.json")
-KERNEL_SOURCES = ["paper_2109_04996_amd/csrc/apply_kernel.h", "paper_2109_04996_amd/csrc/apply_launch.h"]
+KERNEL_SOURCES = ["paper_2109_04996_amd/csrc/colloc_kernel.h", "paper_2109_04996_amd/csrc/apply_launch.h"]
+KERNEL_NAME = "hx::k_colloc<8, 1, double, double, false, true>"
 
 
 def kernel_hash() -> str:
@@ -159,6 +160,8 @@ def main():
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build measures the single-GPU "
@@ -181,6 +184,17 @@ def main():
     n, E = mesh["nnodes"], mesh["nelem"]
     x = pr.to_dev(uniform_vector(n, 1))
     y = pr.zeros()
+    if a.pmc_run:
+        # reference copy of known size (1 GiB read + 1 GiB written) for scaling the counters
+        ref_a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
+        ref_b = torch.empty_like(ref_a)
+        ref_b.copy_(ref_a)
+        for _ in range(6):
+            pr.apply(x, y)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(pmc_run=True, kernel=KERNEL_NAME, kernel_hash=kernel_hash(), workload=f"bp5_p{p}_n{N}",
+                              copy_bytes=2 << 30, colors=pr.stats["ncolors"])), flush=True)
+        return
     print(f"[bench] n={n} E={E} colors={pr.stats['ncolors']}; timing {a.steps} applies", file=sys.stderr, flush=True)
     total_ms, wall, per = time_applies(pr, x, y, a.steps, a.warmup)
     ms = total_ms / a.steps
@@ -195,7 +209,7 @@ def main():
             traffic = c.get("hbm_bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="hx::k_apply<8,8,MODE_COLLOC,1,double,double,false>",
+                kernel=KERNEL_NAME,
                 launches_per_apply=ncol, algorithmic_bytes_per_launch=round(ab["total"] / ncol),
                 avg_launch_us=round(1e3 * ms / ncol, 2), algorithmic_bytes_per_dof=round(ab["total"] / n, 2),
                 kernel_hash=kernel_hash())

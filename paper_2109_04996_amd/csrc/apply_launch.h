@@ -13,12 +13,19 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     // line-per-thread collocated kernel
     using CF = CollocCfg<P>;
     const hx_mesh_s &m = *op.mesh;
+    const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
       const int64_t nb = (e1 - e0 + CF::EPB - 1) / CF::EPB;
-      hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s, a.idx, a.own,
-                         qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1);
+      if (m.idx_rows.ptr)
+        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, true>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
+                           m.idx_rows.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
+                           a.order, e0, e1, zero);
+      else
+        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, false>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
+                           a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0,
+                           e1, zero);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_colloc launch");

@@ -3,7 +3,7 @@
 // Same operator as MODE_COLLOC of apply_kernel.h (Benchmarks section: integration
 // on the (p+1)^3 GLL nodes, so the basis evaluation is the identity and only the
 // 1D derivative matrix D acts; libCEED section: G^T B^T D B G fused into one
-// pass), organised for gfx950's LDS:
+// pass), organised for gfx950:
 //
 // * every contraction runs on a whole line held in one thread's registers. The
 //   P^2 threads of an element take the lines along r3 (thread = (i, j)), then
@@ -19,9 +19,15 @@
 //   wave-uniform addresses (scalar loads), never from LDS.
 // * two LDS buffers per element; for P = 8 one element fills one wavefront and
 //   a workgroup is one wavefront, so the workgroup barriers are cheap.
+// * memory: the pointwise data streams with nontemporal loads, two planes ahead of
+//   use (scheduling barriers keep the compiler from hoisting all 48 loads); every
+//   load is branch-free -- a branch around a load makes the compiler wait for all
+//   outstanding loads at the join -- so lanes past the last element read a valid
+//   element, and the read-modify-write loads of nodes an element owns read a
+//   zero buffer instead.
 //
 // Scatter as in apply_kernel.h: no atomics; element colors, and the ownership bit
-// decides between a store and a read-modify-write.
+// decides between a store (owner) and a read-modify-write.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,11 +35,6 @@
 #include <cstdint>
 
 namespace hx {
-
-// minimum wavefronts per SIMD the register allocator must allow (occupancy hint)
-#ifndef HX_COLLOC_MIN_WAVES
-#define HX_COLLOC_MIN_WAVES 1
-#endif
 
 template <int P>
 struct CollocCfg {
@@ -44,7 +45,6 @@ struct CollocCfg {
   static constexpr int PL = P * LS;       // plane stride
   static constexpr int BUF = P * PL;      // one buffer
 };
-
 
 // Even-odd form of the GLL derivative matrix. The GLL nodes are symmetric about 0, so
 // D[P-1-i][P-1-l] = -D[i][l] (centro-antisymmetric), and y = D u splits into two half-size
@@ -135,24 +135,30 @@ __device__ __forceinline__ void eo_apply_t(const T *__restrict__ C0, const T (&v
   }
 }
 
-template <int P, int NC, typename T, typename TQ, bool EOUT>
-__global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
+// ROWS: idx holds one base id per r1-row ([e][k][j], node (i, j, k) = base + i) instead of
+// one id per node.
+template <int P, int NC, typename T, typename TQ, bool EOUT, bool ROWS>
+__global__ void __launch_bounds__(CollocCfg<P>::THREADS)
     k_colloc(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
              const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ order,
-             int64_t e_begin, int64_t e_end) {
+             int64_t e_begin, int64_t e_end, const T *__restrict__ zero) {
   using CF = CollocCfg<P>;
   constexpr int P2 = CF::P2, P3 = P2 * P, EPB = CF::EPB, LS = CF::LS, PL = CF::PL;
   __shared__ T s0[EPB][CF::BUF];
   __shared__ T s1[EPB][CF::BUF];
 
   const int tid = threadIdx.x;
+  // XCD-aware block order: hardware deals consecutive blocks round-robin to the 8 XCDs;
+  // give each XCD a contiguous run of (spatially sorted) elements.
   const int G = gridDim.x, bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3, base = G >> 3, rem = G & 7;
   const int eb = xcd * base + (xcd < rem ? xcd : rem) + loc;
   const int slot = tid / P2, lt = tid - slot * P2;
   const int a = lt % P, b = lt / P;
-  const int64_t e = e_begin + (int64_t)eb * EPB + slot;
+  const int64_t e_first = e_begin + (int64_t)eb * EPB;  // first element of this workgroup (always valid)
+  const int64_t e = e_first + slot;
   const bool live = e < e_end;
+  const int64_t ee = live ? e : e_first;  // every lane addresses a valid element
   T *const S0 = s0[slot];
   T *const S1 = s1[slot];
   const T *const C = Dg + P * P;  // even-odd coefficients
@@ -160,19 +166,22 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
 #define AT(i, j, k) ((k) * PL + (j) * LS + (i))
 
   int32_t nid[P];
-  uint32_t ob = 0;
-  if (live) {
+  if constexpr (ROWS) {
 #pragma unroll
-    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + b * P + a);
-    ob = own[e * P2 + b * P + a];
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P2 + k * P + b) + a;
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P3 + k * P2 + b * P + a);
   }
-  const TQ *qe = qd + e * (int64_t)(6 * P3) + b * P + a;
+  // a masked lane counts as owner of all its nodes: its read-modify-write loads read zeros
+  const uint32_t ob = live ? (uint32_t)own[ee * P2 + b * P + a] : 0xffffu;
 
   // two planes of pointwise data in flight: plane k+2 is requested while plane k is used
+  const TQ *const qe = qd + ee * (6 * P3) + b * P + a;
   T ga[6], gb[6];
   auto load_plane = [&](T(&g)[6], int k) {
 #pragma unroll
-    for (int m = 0; m < 6; ++m) g[m] = live ? (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2) : T(0);
+    for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2);
   };
 
 #pragma unroll 1
@@ -182,7 +191,7 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
     {
       T u[P];
 #pragma unroll
-      for (int k = 0; k < P; ++k) u[k] = live ? x[(int64_t)nid[k] * NC + c] : T(0);
+      for (int k = 0; k < P; ++k) u[k] = x[(int64_t)nid[k] * NC + c];
       load_plane(ga, 0);
       if constexpr (P > 1) load_plane(gb, 1);
       __builtin_amdgcn_sched_barrier(0);
@@ -227,8 +236,7 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
     // this launch touches these nodes)
     T old[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k)
-      old[k] = (EOUT || !live || (ob & (1u << k))) ? T(0) : y[(int64_t)nid[k] * NC + c];
+    for (int k = 0; k < P; ++k) old[k] = *((EOUT || (ob & (1u << k))) ? zero : y + (int64_t)nid[k] * NC + c);
     // transposed r3 derivative in registers: yt[m] = sum_k D[k][m] vt[k]
     T yt[P];
     eo_apply_t<P, T>(C, vt, yt);
@@ -249,7 +257,7 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
       for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
     }
     __syncthreads();
-    // ---- sum the three parts on lines along r3 and scatter
+    // ---- sum the three parts on lines along r3; store the E-vector or scatter
     if (live) {
       if constexpr (EOUT) {
         T *ye = y + ((int64_t)order[e] * NC + c) * P3 + b * P + a;
@@ -257,7 +265,8 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS, HX_COLLOC_MIN_WAVES)
         for (int k = 0; k < P; ++k) ye[k * P2] = yt[k] + S0[AT(a, b, k)] + S1[AT(a, b, k)];
       } else {
 #pragma unroll
-        for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + (yt[k] + S0[AT(a, b, k)] + S1[AT(a, b, k)]);
+        for (int k = 0; k < P; ++k)
+          y[(int64_t)nid[k] * NC + c] = old[k] + (yt[k] + S0[AT(a, b, k)] + S1[AT(a, b, k)]);
       }
     }
     if constexpr (NC > 1) __syncthreads();

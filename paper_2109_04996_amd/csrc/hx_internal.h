@@ -81,10 +81,12 @@ struct hx_mesh_s {
   std::vector<int64_t> color_start;  // ncolors + 1
   std::vector<double> h_xyz;         // nnodes*3
   hx::DevBuf<int32_t> idx;           // [E_internal][P^3] node ids
+  hx::DevBuf<int32_t> idx_rows;      // [E_internal][P^2] first id of each r1-row (empty unless all rows are runs)
   hx::DevBuf<uint16_t> own;          // [E_internal][P^2] bit k: this element writes node (i,j,k) first
   hx::DevBuf<int32_t> order_d;       // internal position -> caller element id
   hx::DevBuf<double> xyz;            // nnodes*3
   hx::DevBuf<uint8_t> freemask;      // nnodes, 1 = free node
+  hx::DevBuf<double> zeros;          // 64 zeros: target of masked read-modify-write loads
 };
 
 struct hx_op_s {

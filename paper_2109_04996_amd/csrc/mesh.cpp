@@ -205,12 +205,13 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
   const int ncol = std::min(n1, n2);
   m->ncolors = ncol;
 
-  // internal order: color-major, Morton order inside a color
+  // internal order: color-major, Morton order inside a color, reversed on odd colors so each
+  // color's launch starts where the previous one ended (its nodes are then still in cache)
   m->order.resize(nelem);
   std::iota(m->order.begin(), m->order.end(), 0);
   std::stable_sort(m->order.begin(), m->order.end(), [&](int32_t a, int32_t b) {
     if (col[a] != col[b]) return col[a] < col[b];
-    return mk[a] < mk[b];
+    return (col[a] & 1) ? mk[a] > mk[b] : mk[a] < mk[b];
   });
   m->color_start.assign(ncol + 1, 0);
   for (int64_t e = 0; e < nelem; ++e) m->color_start[col[e] + 1]++;
@@ -251,6 +252,31 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
         }
   }
 
+  // compressed restriction: one base id per row along r1 when every row of every element holds
+  // consecutive ids (node (i, j, k) = base[j][k] + i); the fused kernels then read P^2 instead of
+  // P^3 indices per element
+  {
+    bool rows = true;
+    std::vector<int32_t> rb((size_t)nelem * P2);
+    for (int64_t t = 0; t < nelem && rows; ++t)
+      for (int r = 0; r < P2 && rows; ++r) {
+        const int32_t *row = idx.data() + (size_t)t * P3 + (size_t)r * P;
+        for (int i = 1; i < P; ++i)
+          if (row[i] != row[0] + i) {
+            rows = false;
+            break;
+          }
+        rb[(size_t)t * P2 + r] = row[0];
+      }
+    if (rows) {
+      hipError_t e = m->idx_rows.upload(rb.data(), rb.size());
+      if (e != hipSuccess) {
+        delete m;
+        return hx::hip_fail(e, "mesh upload");
+      }
+    }
+  }
+
   std::vector<uint8_t> fm(nnodes, 1);
   m->nfree = nnodes;
   if (dirichlet) {
@@ -265,7 +291,8 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       (e = m->own.upload(own.data(), own.size())) != hipSuccess ||
       (e = m->order_d.upload(m->order.data(), m->order.size())) != hipSuccess ||
       (e = m->xyz.upload(node_xyz, (size_t)nnodes * 3)) != hipSuccess ||
-      (e = m->freemask.upload(fm.data(), fm.size())) != hipSuccess) {
+      (e = m->freemask.upload(fm.data(), fm.size())) != hipSuccess ||
+      (e = m->zeros.upload(std::vector<double>(64, 0.0).data(), 64)) != hipSuccess) {
     delete m;
     return hx::hip_fail(e, "mesh upload");
   }
