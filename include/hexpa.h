@@ -237,6 +237,9 @@ typedef struct {
   double inner_rtol;   /* IR: inner FP32 solve tolerance                      */
   int inner_maxit;     /* IR: inner iteration cap per outer step              */
   int inner_qdata;     /* IR: HX_FP64 or HX_FP32 geometric factors            */
+  int flexible;        /* 1: flexible CG (Polak-Ribiere beta) for preconditioners
+                          that are not exactly linear or symmetric (HX_BF16
+                          Chebyshev); 0: plain PCG                               */
 } hx_solve_opts;
 
 typedef struct {
@@ -252,7 +255,7 @@ typedef struct {
 
 /* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
- * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata. */
+ * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata, flexible 0. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:

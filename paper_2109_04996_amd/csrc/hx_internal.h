@@ -105,8 +105,9 @@ struct hx_op_s {
   hx::DevBuf<double> red;      // reduction partials and device scalars
   hx::DevBuf<double> diag;     // assembled diagonal (cached)
   bool diag_valid = false;
-  // bf16 operator tables (made on demand)
-  hx::DevBuf<uint16_t> tab_bf16;
+  // bf16 matrix-core operator: FP32 tables and a bfloat16 copy of qdata (made on demand)
+  hx::DevBuf<float> tab_bf16;
+  hx::DevBuf<uint16_t> qdata_bf16;
 };
 
 namespace hx {

@@ -34,7 +34,7 @@ constexpr int kVecThreads = 256;
 constexpr int kVecBlocks = 1024;
 
 enum { S_RZ = 0, S_PAP, S_ALPHA, S_RZNEW, S_BETA, S_RR, S_FLAG, S_BB, S_TMP, S_NSCAL = 16 };
-enum { FIN_SUM = 0, FIN_PAP, FIN_RZ_RR, FIN_RZ };
+enum { FIN_SUM = 0, FIN_PAP, FIN_RZ_RR, FIN_RZ, FIN_FLEX };
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -79,6 +79,27 @@ __global__ void __launch_bounds__(kVecThreads) k_dot(int64_t n, const T *__restr
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// sum_t r_t z_t and sum_t (r_t - rp_t) z_t (flexible CG)
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_dot_flex(int64_t n, const T *__restrict__ r, const T *__restrict__ rp,
+                                                            const T *__restrict__ z, double *__restrict__ part0,
+                                                            double *__restrict__ part2) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double s0 = 0.0, s2 = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const double zz = (double)z[t];
+    s0 += (double)r[t] * zz;
+    s2 += ((double)r[t] - (double)rp[t]) * zz;
+  }
+  s0 = block_sum(s0);
+  s2 = block_sum(s2);
+  if (threadIdx.x == 0) {
+    part0[blockIdx.x] = s0;
+    part2[blockIdx.x] = s2;
+  }
+}
+
 // one block: reduce the partials (p1 optional) and derive the CG scalars
 __global__ void __launch_bounds__(kVecThreads) k_final(const double *__restrict__ p0, const double *__restrict__ p1,
                                                          int nb, double *__restrict__ S, int what, int slot) {
@@ -108,6 +129,15 @@ __global__ void __launch_bounds__(kVecThreads) k_final(const double *__restrict_
       S[S_BETA] = (rz_old != 0.0) ? a / rz_old : 0.0;
       S[S_RZ] = a;
       if (!(a > 0.0) && b > 0.0) S[S_FLAG] = 2.0;
+      if (!isfinite(a) || !isfinite(b)) S[S_FLAG] = 3.0;
+      break;
+    }
+    case FIN_FLEX: {  // flexible CG: a = r'z, b = (r - r_prev)'z; beta = b / r'z of the previous step
+      const double rz_old = S[S_RZ];
+      S[S_RZNEW] = a;
+      S[S_BETA] = (rz_old != 0.0) ? b / rz_old : 0.0;
+      S[S_RZ] = a;
+      if (!(a > 0.0) && S[S_RR] > 0.0) S[S_FLAG] = 2.0;
       if (!isfinite(a) || !isfinite(b)) S[S_FLAG] = 3.0;
       break;
     }
@@ -153,18 +183,19 @@ __global__ void __launch_bounds__(kVecThreads) k_jacobi(int64_t n, const T *__re
   if (threadIdx.x == 0) part_rz[blockIdx.x] = s;
 }
 
-// x += alpha p; r -= alpha m w; with JAC also z = dinv r; partials r'z (JAC) and r'r
+// x += alpha p; r -= alpha m w; with JAC also z = dinv r; partials r'z (JAC) and r'r; rp (if given) = old r
 template <typename T, int NC, bool JAC>
 __global__ void __launch_bounds__(kVecThreads)
     k_update(int64_t n, const double *__restrict__ S, T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r,
              const T *__restrict__ w, const uint8_t *__restrict__ fm, const T *__restrict__ dinv, T *__restrict__ z,
-             double *__restrict__ part_rz, double *__restrict__ part_rr) {
+             double *__restrict__ part_rz, double *__restrict__ part_rr, T *__restrict__ rp) {
   const T alpha = (T)S[S_ALPHA];
   int64_t lo, hi;
   slice(n, lo, hi);
   double srz = 0.0, srr = 0.0;
   for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
     x[t] += alpha * p[t];
+    if (rp) rp[t] = r[t];
     const T rv = is_free<NC>(fm, t) ? r[t] - alpha * w[t] : T(0);
     r[t] = rv;
     srr += (double)rv * (double)rv;
@@ -278,7 +309,7 @@ double tridiag_max_eig(const std::vector<double> &d, const std::vector<double> &
 
 template <typename T>
 struct Vecs {
-  T *r, *z, *p, *w, *dinv, *cd, *ct, *x;
+  T *r, *z, *p, *w, *dinv, *cd, *ct, *x, *rp;
 };
 
 struct Ctx {
@@ -286,7 +317,7 @@ struct Ctx {
   hipStream_t s;
   int64_t n;
   int nc;
-  double *part0, *part1, *S;
+  double *part0, *part1, *S, *part2;
   double *hS;  // pinned host copy of S
   int applies = 0;
 };
@@ -350,9 +381,10 @@ using PrecFn = std::function<hx_status(const T *r, T *z)>;
 // go through pc. Stops when r'r <= stop2, at maxit, or on breakdown.
 template <typename T>
 hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, double rr0, double stop2, int maxit,
-                   int check_every, int *iters, double *rr_out) {
+                   int check_every, bool flexible, int *iters, double *rr_out) {
   HX_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * c.n, c.s));
   HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, c.s));
+  flexible = flexible && pc;  // Jacobi is linear and symmetric: plain CG
   if (!pc) {
     LAUNCH_V((k_jacobi<T>), c.n, v.dinv, v.r, v.z, c.part0);
   } else {
@@ -363,21 +395,31 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
   HX_HIP(hipMemcpyAsync(v.p, v.z, sizeof(T) * c.n, hipMemcpyDeviceToDevice, c.s));
   int it = 0;
   double rr = rr0;
+  T *rp = flexible ? v.rp : nullptr;
   while (it < maxit && rr > stop2) {
     if (hx_status st = apply_T(c, v.p, v.w, op_prec)) return st;
     LAUNCH_V((k_dot<T>), c.n, v.p, v.w, c.part0);
     FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
     const uint8_t *fm = c.op.mesh->freemask.ptr;
     if (!pc) {
-      if (c.nc == 1) LAUNCH_V((k_update<T, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
-      else LAUNCH_V((k_update<T, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+      if (c.nc == 1) LAUNCH_V((k_update<T, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
+      else LAUNCH_V((k_update<T, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
+      FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
     } else {
-      if (c.nc == 1) LAUNCH_V((k_update<T, 1, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
-      else LAUNCH_V((k_update<T, 3, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1);
+      if (c.nc == 1) LAUNCH_V((k_update<T, 1, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
+      else LAUNCH_V((k_update<T, 3, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
       if (hx_status st = (*pc)(v.r, v.z)) return st;
-      LAUNCH_V((k_dot<T>), c.n, v.r, v.z, c.part0);
+      if (flexible) {
+        // Polak-Ribiere beta = (r - r_prev)'z / r_prev'z_prev keeps CG robust with a preconditioner
+        // that is not exactly linear or symmetric (rounded operator)
+        FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_RR);
+        LAUNCH_V((k_dot_flex<T>), c.n, v.r, v.rp, v.z, c.part0, c.part2);
+        FINAL(c.part0, c.part2, FIN_FLEX, 0);
+      } else {
+        LAUNCH_V((k_dot<T>), c.n, v.r, v.z, c.part0);
+        FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
+      }
     }
-    FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
     LAUNCH_V((k_pupd<T>), c.n, c.S, v.z, v.p);
     HX_HIP(hipGetLastError());
     ++it;
@@ -397,7 +439,7 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
   return HX_OK;
 }
 
-// Lanczos estimate of lambda_max(D^-1 A): `steps` Jacobi-PCG iterations from a seeded random right-hand
+// Lanczos estimate of the largest eigenvalue of D^-1 A: `steps` Jacobi-PCG iterations from a seeded random right-hand
 // side; the CG coefficients give the Lanczos tridiagonal T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
 // T_{j,j+1} = sqrt(beta_j)/alpha_j, whose largest eigenvalue approaches lambda_max from below.
 hx_status lanczos_lambda_max(Ctx &c, const Vecs<double> &v, int steps, double *lmax) {
@@ -418,8 +460,8 @@ hx_status lanczos_lambda_max(Ctx &c, const Vecs<double> &v, int steps, double *l
     if (hx_status st = apply_T(c, v.p, v.w, HX_FP64)) return st;
     LAUNCH_V((k_dot<double>), c.n, v.p, v.w, c.part0);
     FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
-    if (c.nc == 1) LAUNCH_V((k_update<double, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1);
-    else LAUNCH_V((k_update<double, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1);
+    if (c.nc == 1) LAUNCH_V((k_update<double, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1, (double *)nullptr);
+    else LAUNCH_V((k_update<double, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, c.op.mesh->freemask.ptr, v.dinv, v.z, c.part0, c.part1, (double *)nullptr);
     FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
     LAUNCH_V((k_pupd<double>), c.n, c.S, v.z, v.p);
     if (hx_status e = read_scalars(c)) return e;
@@ -441,9 +483,9 @@ hx_status lanczos_lambda_max(Ctx &c, const Vecs<double> &v, int steps, double *l
 
 template <typename T>
 hx_status carve(DevBuf<T> &buf, int64_t n, Vecs<T> &v) {
-  if (buf.count < (size_t)(8 * n)) HX_HIP(buf.alloc((size_t)8 * n));
+  if (buf.count < (size_t)(9 * n)) HX_HIP(buf.alloc((size_t)9 * n));
   T *b = buf.ptr;
-  v = Vecs<T>{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n, b + 7 * n};
+  v = Vecs<T>{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n, b + 7 * n, b + 8 * n};
   return HX_OK;
 }
 
@@ -474,6 +516,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->inner_rtol = 1e-4;
   o->inner_maxit = 200;
   o->inner_qdata = HX_FP64;
+  o->flexible = 0;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -502,10 +545,11 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   const int NC = op->ncomp;
   const auto t_setup0 = std::chrono::steady_clock::now();
 
-  if (op->red.count < (size_t)(2 * kVecBlocks + S_NSCAL)) HX_HIP(op->red.alloc(2 * kVecBlocks + S_NSCAL));
+  if (op->red.count < (size_t)(3 * kVecBlocks + S_NSCAL)) HX_HIP(op->red.alloc(3 * kVecBlocks + S_NSCAL));
   PinnedHost hs;
   HX_HIP(hipHostMalloc(reinterpret_cast<void **>(&hs.p), sizeof(double) * S_NSCAL));
-  Ctx c{*op, s, n, NC, op->red.ptr, op->red.ptr + kVecBlocks, op->red.ptr + 2 * kVecBlocks, hs.p, 0};
+  Ctx c{*op, s, n, NC, op->red.ptr, op->red.ptr + kVecBlocks, op->red.ptr + 3 * kVecBlocks,
+        op->red.ptr + 2 * kVecBlocks, hs.p, 0};
 
   Vecs<double> v;
   if (hx_status st = carve(op->work, n, v)) return st;
@@ -596,7 +640,8 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     if (cheb) pc = (o.cheb_prec == HX_FP64) ? &pc64 : &pc32;
     int it = 0;
     double rre = 0;
-    result = pcg_core<double>(c, v, pc, HX_FP64, rr, o.rtol * o.rtol * bb, o.maxit, o.check_every, &it, &rre);
+    result = pcg_core<double>(c, v, pc, HX_FP64, rr, o.rtol * o.rtol * bb, o.maxit, o.check_every, o.flexible != 0,
+                              &it, &rre);
     LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
     info->iterations = it;
     info->rel_residual = std::sqrt(rre) / bn;
@@ -623,7 +668,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       double rri = 0;
       // inner r'r starts at ~1 (the residual is normalised)
       hx_status st = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, cg_prec, 1.0, o.inner_rtol * o.inner_rtol,
-                                     o.inner_maxit, std::min(o.check_every, o.inner_maxit), &it, &rri);
+                                     o.inner_maxit, std::min(o.check_every, o.inner_maxit), o.flexible != 0, &it, &rri);
       if (st == HX_EBREAKDOWN && it > 1) st = HX_OK;  // keep the partial correction; the FP64 residual judges it
       if (st) return st;
       inner_total += it;

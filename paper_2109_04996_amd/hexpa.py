@@ -53,7 +53,8 @@ class hx_solve_opts(C.Structure):
     _fields_ = [("mode", C.c_int), ("precond", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
                 ("check_every", C.c_int), ("use_x0", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("cheb_prec", C.c_int), ("lanczos_steps", C.c_int),
-                ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int)]
+                ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
+                ("flexible", C.c_int)]
 
 
 class hx_solve_info(C.Structure):

@@ -49,6 +49,11 @@ class Problem:
         hx.hx_op_apply_f32(self.h_op, qdata_prec, x, y)
         return y
 
+    def apply_bf16(self, x, y=None):
+        y = self.zeros(self.torch.float32) if y is None else y
+        hx.hx_op_apply_bf16(self.h_op, x, y)
+        return y
+
     def apply_elem(self, x):
         P3 = (self.p + 1) ** 3
         ye = self.torch.empty(self.mesh["nelem"] * self.ncomp * P3, dtype=self.torch.float64, device="cuda")

@@ -111,3 +111,16 @@ def test_failures_reported():
         zero = torch.zeros_like(b)
         x2, info = pr.solve(zero)
         assert torch.count_nonzero(x2) == 0
+
+
+@pytest.mark.parametrize("mode", [hx.HX_SOLVE_FP64, hx.HX_SOLVE_IR])
+def test_chebyshev_bf16_flexible(mode):
+    mesh, pr, b, A, bo, free = _setup(4, 6, 8, "gauss", warp="B")
+    with pr:
+        _, ij = pr.solve(b, rtol=1e-8)
+        x, info = pr.solve(b, rtol=1e-8, mode=mode, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_BF16, flexible=1)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        assert info["iterations"] < ij["iterations"], (info, ij)
+        xd = solvers.direct_solve(A, bo, free)
+        xo, _, _ = solvers.jacobi_pcg(A, bo, free, tol=1e-8)
+        assert np.linalg.norm(x.cpu().numpy() - xd) <= 10 * np.linalg.norm(xo - xd) + 1e-12
