@@ -125,6 +125,104 @@ def solves(pr, mass_pr, maxit=20000):
     return out
 
 
+def _timed_solve(pr, b, ref=None, **o):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = pr.solve(b, rtol=o.pop("rtol", 1e-8), maxit=o.pop("maxit", 40000), check_every=25,
+                       raise_on_error=False, **o)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = dict(status=info["status"], iterations=info["iterations"], outer=info["outer_iterations"],
+               applies=info["operator_applies"], seconds=round(info["solve_seconds"], 4),
+               setup_seconds=round(info["setup_seconds"], 4), wall_seconds=round(wall, 4),
+               true_rel_residual=info["true_rel_residual"])
+    if ref is not None:
+        rec["rel_error_vs_fp64_reference"] = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+    if info.get("fallback_used"):
+        rec["fallback_used"] = 1
+        rec["fallback_iterations"] = info["fallback_iterations"]
+    return x, rec
+
+
+def suite_vector_ir(p=6, N=30):
+    """Vector diffusion, 3 interleaved components, q = p+2 Gauss, FP64 PCG vs FP32-operator IR."""
+    import numpy as np
+
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd.inputs import lattice_mesh
+    from paper_2109_04996_amd.problem import Problem
+    print(f"[bench] vector IR suite p={p} N={N}", file=sys.stderr, flush=True)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    pr = Problem(N, p, p + 2, "gauss", "diffusion", ncomp=3, mesh=mesh)
+    mass = Problem(N, p, p + 2, "gauss", "mass", ncomp=3, mesh=mesh)
+    X = pr.xyz
+    f = 3 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+    b = mass.apply(pr.to_dev((f[:, None] * np.array([1.0, -1.0, 0.5])[None, :]).ravel()))
+    mass.close()
+    ref, _ = pr.solve(b, rtol=1e-12, maxit=100000, check_every=50)
+    out = dict(workload=f"BP4-type vector diffusion, 3 components, p={p}, q={p + 2} Gauss, mesh A {N}^3, "
+                        f"{mesh['nnodes']} nodes x 3, rtol 1e-8; reference: FP64 PCG to 1e-12")
+    _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
+    _, out["ir_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP64,
+                                                 inner_maxit=2000)
+    _, out["ir_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP32,
+                                                 inner_maxit=2000)
+    pr.close()
+    return out
+
+
+def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
+    """Scalar variable-coefficient diffusion, p=6, q=8: FP64 PCG vs FP32/bf16-matrix-core Chebyshev forms."""
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd import learned
+    print(f"[bench] kappa Chebyshev suite p={p} N={N}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    pr, b = learned.problem_with_kappa(N, p, p + 2, "gauss", kappa_seed)
+    setup = time.perf_counter() - t0
+    ref, _ = pr.solve(b, rtol=1e-12, maxit=100000, check_every=50)
+    out = dict(workload=f"diffusion with kappa = exp(g), g a seeded random-Fourier-feature field (seed {kappa_seed}, "
+                        f"contrast ~1e2), p={p}, q={p + 2} Gauss, mesh A {N}^3, {pr.mesh['nnodes']} DOFs, b = B 1, "
+                        f"rtol 1e-8; reference: FP64 PCG to 1e-12", setup_seconds=round(setup, 2))
+    _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
+    _, out["fp64_cg_cheb4_fp32op"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32)
+    _, out["fp64_fcg_cheb4_bf16mfma"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_BF16,
+                                                     flexible=1)
+    _, out["ir_fp32op_cheb4_bf16mfma"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
+                                                      cheb_prec=hx.HX_BF16, inner_qdata=hx.HX_FP32, flexible=1,
+                                                      inner_maxit=500)
+    pr.close()
+    return out
+
+
+def suite_learned(p=5, N_train=8, N_eval=40, train_seeds=(1000, 1001, 1002, 1003), eval_seed=100):
+    """Learned element preconditioner: training cost, then FCG vs Jacobi and Chebyshev PCG on a held-out field."""
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd import learned
+    print(f"[bench] learned suite p={p}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    X, T = learned.training_set(p, p + 2, "gauss", N_train, train_seeds, rows_per_snapshot=420)
+    t_data = time.perf_counter() - t0
+    net, info = learned.train(X, T, epochs=100, batch=256, lr=1e-3)
+    pr, b = learned.problem_with_kappa(N_eval, p, p + 2, "gauss", eval_seed)
+    res = learned.compare_solves(pr, b, net)
+    out = dict(workload=f"diffusion with kappa (held-out seed {eval_seed}), p={p}, q={p + 2} Gauss, mesh A "
+                        f"{N_eval}^3, {pr.mesh['nnodes']} DOFs, b = B 1, rtol 1e-8",
+               training=dict(samples=int(X.shape[0]), data_seconds=round(t_data, 2),
+                             train_seconds=round(info["seconds"], 2), steps=info["steps"],
+                             first_loss=info["first_loss"], final_loss=info["final_loss"],
+                             train_problems=f"{len(train_seeds)} coefficient seeds {train_seeds}, mesh {N_train}^3"),
+               **res)
+    base = min(res["jacobi"]["seconds"], res["chebyshev4"]["seconds"])
+    gain = base / max(res["learned"]["seconds"], 1e-9)
+    out["learned_speedup_vs_best_fallback"] = round(gain, 3)
+    saved = base - res["learned"]["seconds"]
+    out["break_even_solves"] = (round((t_data + info["seconds"]) / saved, 1) if saved > 0 else None)
+    pr.close()
+    hx.hx_mlp_destroy(net)
+    return out
+
+
 def cpu_baseline(p: int, budget_s: float = 20.0):
     """The oracle (scipy CSR SpMV of the assembled matrix) on a bounded sample of the same workload."""
     import numpy as np
@@ -160,6 +258,8 @@ def main():
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--all", action="store_true",
+                    help="also run the vector-IR, variable-coefficient Chebyshev and learned-preconditioner suites")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
     a = ap.parse_args()
@@ -230,6 +330,14 @@ def main():
                              **solves(pr, mass_pr))
         mass_pr.close()
     pr.close()
+    del x, y
+    if a.all:
+        torch.cuda.empty_cache()
+        out["vector_ir"] = suite_vector_ir()
+        torch.cuda.empty_cache()
+        out["kappa_chebyshev"] = suite_kappa_cheb()
+        torch.cuda.empty_cache()
+        out["learned"] = suite_learned()
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)

@@ -66,6 +66,7 @@ enum { HX_FP64 = 0, HX_FP32 = 1, HX_BF16 = 2 };
 typedef struct hx_mesh_s *hx_mesh;
 typedef struct hx_basis_s *hx_basis;
 typedef struct hx_op_s *hx_op;
+typedef struct hx_mlp_s *hx_mlp;  /* two-layer network (learned preconditioner) */
 typedef void *hx_stream; /* hipStream_t */
 
 /* Text of the last error on the calling thread ("" if none). Never NULL. */
@@ -218,7 +219,7 @@ void hx_op_destroy(hx_op op);
 /* Solves                                                                    */
 /* ------------------------------------------------------------------------ */
 
-enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2 };
+enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2, HX_PC_MLP = 3 };
 enum { HX_SOLVE_FP64 = 0, HX_SOLVE_IR = 1 };
 
 typedef struct {
@@ -240,6 +241,14 @@ typedef struct {
   int flexible;        /* 1: flexible CG (Polak-Ribiere beta) for preconditioners
                           that are not exactly linear or symmetric (HX_BF16
                           Chebyshev); 0: plain PCG                               */
+  hx_mlp mlp;          /* HX_PC_MLP: the trained network (flexible CG is used)  */
+  int fallback;        /* HX_PC_MLP: HX_PC_JACOBI or HX_PC_CHEBYSHEV, run from the
+                          current iterate when the learned solve breaks down or
+                          stalls                                               */
+  int stall_window;    /* HX_PC_MLP: stall = the residual fell by less than     */
+  double stall_factor; /* stall_factor over the last stall_window iterations   */
+  int mlp_mode;        /* HX_PC_MLP: 0: z = network correction; 1: z = D^-1 r plus
+                          the network correction (trained on targets e - D^-1 r) */
 } hx_solve_opts;
 
 typedef struct {
@@ -251,11 +260,14 @@ typedef struct {
   double lam_max;        /* Chebyshev: estimated lambda_max of D^-1 A         */
   double setup_seconds;  /* Chebyshev lambda estimate, diagonal               */
   double solve_seconds;  /* wall time of the iteration                        */
+  int fallback_used;     /* HX_PC_MLP: 1 if the fallback solve ran            */
+  int fallback_iterations; /* iterations of the fallback solve                */
 } hx_solve_info;
 
 /* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
- * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata, flexible 0. */
+ * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata, flexible 0, no network,
+ * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 0. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:
@@ -269,6 +281,77 @@ void hx_solve_opts_default(hx_solve_opts *opts);
  * HX_EBREAKDOWN, HX_ENOMEM, HX_EHIP. */
 hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
                        hx_solve_info *info, hx_stream s);
+
+/* ------------------------------------------------------------------------ */
+/* Two-layer network (learned element preconditioner; not in the paper)      */
+/* ------------------------------------------------------------------------ */
+
+/* y = W2 tanh(W1 x + b1) + b2, FP32 parameters on the device. Parameter vector
+ * layout (hx_mlp_set_params / get_params / loss_grad): W1 [n_hidden][n_in],
+ * b1 [n_hidden], W2 [n_out][n_hidden], b2 [n_out], row-major, FP32. */
+
+/* Weights uniform(-1, 1)/sqrt(fan_in) from a seeded generator, zero biases.
+ * Errors: HX_EINVAL (sizes), HX_ENOMEM, HX_EHIP. */
+hx_status hx_mlp_create(int n_in, int n_hidden, int n_out, uint64_t seed, hx_mlp *out);
+hx_status hx_mlp_get_shape(hx_mlp net, int *n_in, int *n_hidden, int *n_out);
+/* host arrays of n_hidden*(n_in+1) + n_out*(n_hidden+1) floats */
+hx_status hx_mlp_set_params(hx_mlp net, const float *params);
+hx_status hx_mlp_get_params(hx_mlp net, float *params);
+
+/* Y [batch][n_out] = net(X [batch][n_in]); device FP32 arrays. prec HX_FP32:
+ * FP32 arithmetic; HX_BF16: operands rounded to bfloat16 on matrix cores, FP32
+ * accumulation, bf16 hidden activations. Asynchronous. */
+hx_status hx_mlp_forward(hx_mlp net, int prec, const float *X, int64_t batch, float *Y, hx_stream s);
+
+/* Mean squared error over all batch*n_out entries and its gradient with respect
+ * to every parameter (FP32 arithmetic). loss: host double (may be NULL); grads:
+ * host array in the parameter layout (may be NULL). Synchronous. */
+hx_status hx_mlp_loss_grad(hx_mlp net, const float *X, const float *T, int64_t batch, double *loss, float *grads,
+                           hx_stream s);
+
+typedef struct {
+  int epochs;        /* passes over the samples                          */
+  int batch;         /* rows per Adam step (the tail of an epoch is dropped) */
+  double lr, beta1, beta2, eps;  /* Adam                                  */
+  uint64_t seed;     /* minibatch shuffling                               */
+} hx_train_opts;
+
+typedef struct {
+  int64_t steps;
+  double first_loss;  /* loss of the last batch of the first epoch        */
+  double final_loss;  /* loss of the last batch of the last epoch         */
+  double seconds;
+} hx_train_info;
+
+/* Defaults: 200 epochs, batch 256, lr 1e-3, betas 0.9/0.999, eps 1e-8, seed 7. */
+void hx_train_opts_default(hx_train_opts *opts);
+
+/* Adam on the GPU over X [nsamples][n_in], T [nsamples][n_out] (device FP32).
+ * Synchronous. Errors: HX_EINVAL, HX_ENOMEM, HX_EHIP. */
+hx_status hx_mlp_train(hx_mlp net, const float *X, const float *T, int64_t nsamples, const hx_train_opts *opts,
+                       hx_train_info *info, hx_stream s);
+
+/* Learned element preconditioner on a scalar diffusion operator (see the
+ * HX_PC_MLP solve). For a residual r (device FP64 L-vector), element e's network
+ * input is [r_e/|r_e|, log kappa_e - mean(log kappa_e)] (2 (p+1)^3 values) and the
+ * correction is z = G^T (w * |r_e| h_e^2/mean(kappa_e) * net(input)), w = 1 over
+ * the node's multiplicity (0 on constrained nodes), h_e the element size.
+ *   hx_op_mlp_features: X [nelem][2 (p+1)^3] and rnorm [nelem] (device FP32,
+ *     caller element order), the inputs for a residual r.
+ *   hx_op_mlp_targets: T [nelem][(p+1)^3] (device FP32, caller order): the
+ *     training targets err_e / (|r_e| h_e^2 / mean kappa_e) for an error vector.
+ *   hx_op_mlp_precond: z = the correction for r (device FP64), bf16 matrix cores.
+ * Asynchronous. Errors: HX_EINVAL (shapes), HX_EUNSUPPORTED (not scalar
+ * diffusion), HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_mlp_features(hx_op op, const double *r, float *X, float *rnorm, hx_stream s);
+hx_status hx_op_mlp_targets(hx_op op, const double *err, const float *rnorm, float *T, hx_stream s);
+hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, const double *r, double *z, hx_stream s);
+
+/* Checkpoint: 8-byte magic "HXMLP1", int32 n_in, n_hidden, n_out, 0, then the FP32
+ * parameters in the layout above. */
+hx_status hx_mlp_save(hx_mlp net, const char *path);
+hx_status hx_mlp_load(const char *path, hx_mlp *out);
+void hx_mlp_destroy(hx_mlp net);
 
 #ifdef __cplusplus
 }

@@ -141,6 +141,13 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
     delete op;
     return hip_fail(e, "operator allocation");
   }
+  if (kappa && kappa->M > 0) {
+    op->kappa_M = kappa->M;
+    op->kappa_omega.assign(kappa->omega, kappa->omega + 3 * kappa->M);
+    op->kappa_phase.assign(kappa->phase, kappa->phase + kappa->M);
+    op->kappa_scale = kappa->scale;
+    op->kappa_shift = kappa->shift;
+  }
   int bad = 0;
   if (hx_status st = launch_setup_qdata(*op, kappa, s, &bad)) {
     delete op;

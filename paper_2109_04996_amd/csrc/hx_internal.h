@@ -105,6 +105,18 @@ struct hx_op_s {
   hx::DevBuf<double> red;      // reduction partials and device scalars
   hx::DevBuf<double> diag;     // assembled diagonal (cached)
   bool diag_valid = false;
+  // coefficient parameters (kept for the element features of the learned preconditioner)
+  int kappa_M = 0;
+  std::vector<double> kappa_omega, kappa_phase;
+  double kappa_scale = 0.0, kappa_shift = 0.0;
+  // learned preconditioner: element features and work buffers (made on first use)
+  bool mlp_ready = false;
+  hx::DevBuf<float> mlp_logk;      // [n] log kappa at the nodes
+  hx::DevBuf<uint16_t> mlp_feat16; // [E_internal][P^3] centred log kappa, bf16
+  hx::DevBuf<float> mlp_escale;    // [E_internal] h_e^2 / mean kappa_e
+  hx::DevBuf<float> mlp_wmult;     // [n] 1 / multiplicity on free nodes, 0 on constrained ones
+  hx::DevBuf<uint16_t> mlp_x16, mlp_h16;
+  hx::DevBuf<float> mlp_y, mlp_rnorm;
   // bf16 matrix-core operator: FP32 tables and a bfloat16 copy of qdata (made on demand)
   hx::DevBuf<float> tab_bf16;
   hx::DevBuf<uint16_t> qdata_bf16;

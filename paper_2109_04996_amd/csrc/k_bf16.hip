@@ -14,30 +14,15 @@
 //
 // The pointwise operator runs in FP32 on a bfloat16 copy of the stored FP64 qdata. The
 // scatter is the atomic-free colored scatter of the FP64 kernels.
+#include "bf16_util.h"
 #include "hx_internal.h"
 
 namespace hx {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ short to_bf16(float f) {
-  // round to nearest even
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-
-__host__ __device__ inline uint16_t to_bf16_bits(float f) {
-  uint32_t u;
-  memcpy(&u, &f, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+__device__ __forceinline__ short to_bf16(float f) { return (short)f32_to_bf16_bits(f); }
+__device__ __forceinline__ float from_bf16(uint16_t h) { return bf16_bits_to_f32(h); }
 
 // A operand of a table T (rows x cols, row-major, FP32 in LDS), optionally transposed:
 // lane l holds T[l%16][4(l/16)+t] (or T^T), zero outside the table.
@@ -183,7 +168,7 @@ __global__ void __launch_bounds__(64)
 
 __global__ void k_qdata_bf16(int64_t n, const double *__restrict__ a, uint16_t *__restrict__ b) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    b[t] = to_bf16_bits((float)a[t]);
+    b[t] = f32_to_bf16_bits((float)a[t]);
 }
 
 }  // namespace

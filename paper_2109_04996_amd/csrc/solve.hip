@@ -20,7 +20,7 @@
 #include <functional>
 #include <random>
 
-#include "hx_internal.h"
+#include "mlp_internal.h"
 
 extern "C" hx_status hx_op_diagonal(hx_op op, double *diag, hx_stream s);
 
@@ -266,6 +266,14 @@ __global__ void __launch_bounds__(kVecThreads) k_convert(int64_t n, double scale
     b[t] = (TB)(scale * (double)a[t]);
 }
 
+// z = dinv r + t (Jacobi step plus a correction)
+__global__ void __launch_bounds__(kVecThreads) k_jac_plus(int64_t n, const double *__restrict__ dinv,
+                                                            const double *__restrict__ r, const double *__restrict__ t,
+                                                            double *__restrict__ z) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = dinv[i] * r[i] + t[i];
+}
+
 // x += scale * d (FP64 x)
 template <typename TD>
 __global__ void __launch_bounds__(kVecThreads) k_axpy(int64_t n, double scale, const TD *__restrict__ d,
@@ -379,9 +387,13 @@ using PrecFn = std::function<hx_status(const T *r, T *z)>;
 // PCG on vectors of type T. On entry v.r holds the masked right-hand side with r'r = rr0; solves for v.x
 // from 0. Jacobi (and none, with dinv = mask) is fused into the update kernel; other preconditioners
 // go through pc. Stops when r'r <= stop2, at maxit, or on breakdown.
+constexpr hx_status kStalled = -100;  // internal: the residual stopped falling (learned preconditioner)
+
 template <typename T>
 hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, double rr0, double stop2, int maxit,
-                   int check_every, bool flexible, int *iters, double *rr_out) {
+                   int check_every, bool flexible, int *iters, double *rr_out, int stall_window = 0,
+                   double stall_factor = 0.0) {
+  std::vector<std::pair<int, double>> hist{{0, rr0}};  // (iteration, r'r) at the host checks
   HX_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * c.n, c.s));
   HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, c.s));
   flexible = flexible && pc;  // Jacobi is linear and symmetric: plain CG
@@ -431,6 +443,15 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
         *rr_out = rr;
         return fail(HX_EBREAKDOWN, "CG breakdown: p'Ap <= 0, r'z <= 0 or a non-finite scalar (flag " +
                                        std::to_string((int)c.hS[S_FLAG]) + ")");
+      }
+      if (stall_window > 0) {
+        hist.emplace_back(it, rr);
+        for (const auto &h : hist)
+          if (h.first <= it - stall_window && h.first > it - stall_window - check_every && rr > stall_factor * stall_factor * h.second) {
+            *iters = it;
+            *rr_out = rr;
+            return kStalled;
+          }
       }
     }
   }
@@ -517,6 +538,11 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->inner_maxit = 200;
   o->inner_qdata = HX_FP64;
   o->flexible = 0;
+  o->mlp = nullptr;
+  o->fallback = HX_PC_JACOBI;
+  o->stall_window = 20;
+  o->stall_factor = 0.1;
+  o->mlp_mode = 0;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -524,9 +550,20 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   if (!op || !b || !x || !opts || !info) return fail(HX_EINVAL, "null argument");
   const hx_solve_opts &o = *opts;
   if (o.mode != HX_SOLVE_FP64 && o.mode != HX_SOLVE_IR) return fail(HX_EINVAL, "mode must be HX_SOLVE_FP64 or HX_SOLVE_IR");
-  if (o.precond < HX_PC_NONE || o.precond > HX_PC_CHEBYSHEV) return fail(HX_EINVAL, "precond out of range");
+  if (o.precond < HX_PC_NONE || o.precond > HX_PC_MLP) return fail(HX_EINVAL, "precond out of range");
   if (!(o.rtol > 0) || o.maxit < 1 || o.check_every < 1) return fail(HX_EINVAL, "need rtol > 0, maxit >= 1, check_every >= 1");
-  const bool cheb = o.precond == HX_PC_CHEBYSHEV;
+  const bool mlp = o.precond == HX_PC_MLP;
+  if (mlp && !o.mlp) return fail(HX_EINVAL, "HX_PC_MLP needs opts.mlp");
+  if (mlp && o.mode != HX_SOLVE_FP64) return fail(HX_EUNSUPPORTED, "HX_PC_MLP runs in HX_SOLVE_FP64 mode");
+  if (mlp && (op->kind != HX_DIFFUSION || op->ncomp != 1))
+    return fail(HX_EUNSUPPORTED, "the learned preconditioner supports scalar diffusion only");
+  if (mlp && o.fallback != HX_PC_JACOBI && o.fallback != HX_PC_CHEBYSHEV)
+    return fail(HX_EINVAL, "fallback must be HX_PC_JACOBI or HX_PC_CHEBYSHEV");
+  if (mlp && o.mlp_mode != 0 && o.mlp_mode != 1) return fail(HX_EINVAL, "mlp_mode must be 0 or 1");
+  if (mlp && (o.stall_window < 0 || !(o.stall_factor > 0 && o.stall_factor < 1)))
+    return fail(HX_EINVAL, "stall_window >= 0 and 0 < stall_factor < 1");
+  // Chebyshev runs as the preconditioner, or as the fallback of the learned one
+  const bool cheb = o.precond == HX_PC_CHEBYSHEV || (mlp && o.fallback == HX_PC_CHEBYSHEV);
   if (cheb && (o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) || o.lanczos_steps < 2))
     return fail(HX_EINVAL, "Chebyshev needs cheb_degree >= 1, cheb_ratio > 1, lanczos_steps >= 2");
   if (cheb && o.cheb_prec != HX_FP64 && o.cheb_prec != HX_FP32 && o.cheb_prec != HX_BF16)
@@ -636,14 +673,41 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       LAUNCH_V((k_convert<float, double>), n, 1.0, v32.z, z);
       return HX_OK;
     };
-    const PrecFn<double> *pc = nullptr;
-    if (cheb) pc = (o.cheb_prec == HX_FP64) ? &pc64 : &pc32;
+    PrecFn<double> pcm = [&](const double *r, double *z) -> hx_status {
+      if (o.mlp_mode == 0) return mlp_precond_apply(*op, *o.mlp, r, z, s);
+      // Jacobi step plus the network's correction (v.ct is free outside Chebyshev)
+      if (hx_status st = mlp_precond_apply(*op, *o.mlp, r, v.ct, s)) return st;
+      LAUNCH_V(k_jac_plus, n, v.dinv, r, v.ct, z);
+      return HX_OK;
+    };
+    const PrecFn<double> *pc_cheb = cheb ? ((o.cheb_prec == HX_FP64) ? &pc64 : &pc32) : nullptr;
+    const PrecFn<double> *pc = mlp ? &pcm : pc_cheb;
+    const double stop2 = o.rtol * o.rtol * bb;
     int it = 0;
     double rre = 0;
-    result = pcg_core<double>(c, v, pc, HX_FP64, rr, o.rtol * o.rtol * bb, o.maxit, o.check_every, o.flexible != 0,
-                              &it, &rre);
+    // the learned preconditioner is nonlinear in r: flexible CG, with a stall check for the fallback
+    result = pcg_core<double>(c, v, pc, HX_FP64, rr, stop2, o.maxit, o.check_every, o.flexible != 0 || mlp, &it,
+                              &rre, mlp ? o.stall_window : 0, o.stall_factor);
+    if (mlp) HX_HIP(hipMemcpyAsync(v.cd, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));  // x before the learned phase
     LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
     info->iterations = it;
+    if (mlp && (result == HX_EBREAKDOWN || result == kStalled || (result == HX_OK && rre > stop2))) {
+      // judge and fallback: Jacobi or Chebyshev PCG from the current iterate, or from the iterate
+      // before the learned phase when its correction is not finite or did not lower the true residual
+      info->fallback_used = 1;
+      double rr2 = 0;
+      if (hx_status st = residual(&rr2)) return st;
+      if (!std::isfinite(rr2) || rr2 >= rr) {
+        HX_HIP(hipMemcpyAsync(x, v.cd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (hx_status st = residual(&rr2)) return st;
+      }
+      int it2 = 0;
+      result = pcg_core<double>(c, v, o.fallback == HX_PC_CHEBYSHEV ? pc_cheb : nullptr, HX_FP64, rr2, stop2,
+                                std::max(1, o.maxit - it), o.check_every, o.flexible != 0, &it2, &rre);
+      LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
+      info->fallback_iterations = it2;
+      info->iterations += it2;
+    }
     info->rel_residual = std::sqrt(rre) / bn;
   } else {
     // iterative refinement: FP64 residual, FP32 inner PCG on r / ||r||, FP64 update x += ||r|| d

@@ -20,7 +20,7 @@ HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOW
 HX_GAUSS, HX_GLL = 0, 1
 HX_MASS, HX_DIFFUSION = 0, 1
 HX_FP64, HX_FP32, HX_BF16 = 0, 1, 2
-HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV = 0, 1, 2
+HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP = 0, 1, 2, 3
 HX_SOLVE_FP64, HX_SOLVE_IR = 0, 1
 
 STATUS_NAMES = {0: "HX_OK", -1: "HX_EINVAL", -2: "HX_ERANGE", -3: "HX_EUNSUPPORTED", -4: "HX_EGEOM",
@@ -54,13 +54,25 @@ class hx_solve_opts(C.Structure):
                 ("check_every", C.c_int), ("use_x0", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("cheb_prec", C.c_int), ("lanczos_steps", C.c_int),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
-                ("flexible", C.c_int)]
+                ("flexible", C.c_int), ("mlp", C.c_void_p), ("fallback", C.c_int), ("stall_window", C.c_int),
+                ("stall_factor", C.c_double), ("mlp_mode", C.c_int)]
+
+
+class hx_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class hx_train_info(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("first_loss", C.c_double), ("final_loss", C.c_double),
+                ("seconds", C.c_double)]
 
 
 class hx_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int), ("operator_applies", C.c_int),
                 ("rel_residual", C.c_double), ("true_rel_residual", C.c_double), ("lam_max", C.c_double),
-                ("setup_seconds", C.c_double), ("solve_seconds", C.c_double)]
+                ("setup_seconds", C.c_double), ("solve_seconds", C.c_double), ("fallback_used", C.c_int),
+                ("fallback_iterations", C.c_int)]
 
 
 _VP, _I64, _I32P = C.c_void_p, C.c_int64, C.c_void_p
@@ -86,6 +98,20 @@ SIGNATURES = [
     ("hx_op_get_stats", C.c_int, [_VP, C.POINTER(hx_op_stats)]),
     ("hx_op_destroy", None, [_VP]),
     ("hx_solve_opts_default", None, [C.POINTER(hx_solve_opts)]),
+    ("hx_mlp_create", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(_VP)]),
+    ("hx_mlp_get_shape", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("hx_mlp_set_params", C.c_int, [_VP, _VP]),
+    ("hx_mlp_get_params", C.c_int, [_VP, _VP]),
+    ("hx_mlp_forward", C.c_int, [_VP, C.c_int, _VP, _I64, _VP, _VP]),
+    ("hx_mlp_loss_grad", C.c_int, [_VP, _VP, _VP, _I64, C.POINTER(C.c_double), _VP, _VP]),
+    ("hx_train_opts_default", None, [C.c_void_p]),
+    ("hx_mlp_train", C.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, _VP]),
+    ("hx_mlp_save", C.c_int, [_VP, C.c_char_p]),
+    ("hx_mlp_load", C.c_int, [C.c_char_p, C.POINTER(_VP)]),
+    ("hx_mlp_destroy", None, [_VP]),
+    ("hx_op_mlp_features", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("hx_op_mlp_targets", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("hx_op_mlp_precond", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hx_pcg_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(hx_solve_opts), C.POINTER(hx_solve_info), _VP]),
 ]
 
@@ -264,3 +290,87 @@ def hx_pcg_solve(op, b, x, opts: hx_solve_opts, stream=None, raise_on_error=True
     if raise_on_error and code != HX_OK:
         raise HexpaError(code, "hx_pcg_solve", hx_last_error())
     return d
+
+
+# ---------------------------------------------------------------------------- network
+
+def hx_mlp_create(n_in, n_hidden, n_out, seed=7):
+    h = C.c_void_p()
+    _check(load().hx_mlp_create(n_in, n_hidden, n_out, seed, C.byref(h)), "hx_mlp_create")
+    return h
+
+
+def hx_mlp_get_shape(net):
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(load().hx_mlp_get_shape(net, C.byref(a), C.byref(b), C.byref(c)), "hx_mlp_get_shape")
+    return a.value, b.value, c.value
+
+
+def mlp_param_count(n_in, n_hidden, n_out):
+    return n_hidden * (n_in + 1) + n_out * (n_hidden + 1)
+
+
+def hx_mlp_set_params(net, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load().hx_mlp_set_params(net, _ptr(a)), "hx_mlp_set_params")
+
+
+def hx_mlp_get_params(net) -> np.ndarray:
+    out = np.zeros(mlp_param_count(*hx_mlp_get_shape(net)), np.float32)
+    _check(load().hx_mlp_get_params(net, _ptr(out)), "hx_mlp_get_params")
+    return out
+
+
+def hx_mlp_forward(net, prec, X, Y, stream=None):
+    _check(load().hx_mlp_forward(net, prec, _ptr(X), X.shape[0], _ptr(Y), _stream(stream)), "hx_mlp_forward")
+
+
+def hx_mlp_loss_grad(net, X, T, stream=None):
+    loss = C.c_double()
+    g = np.zeros(mlp_param_count(*hx_mlp_get_shape(net)), np.float32)
+    _check(load().hx_mlp_loss_grad(net, _ptr(X), _ptr(T), X.shape[0], C.byref(loss), _ptr(g), _stream(stream)),
+           "hx_mlp_loss_grad")
+    return loss.value, g
+
+
+def hx_train_opts_default(**overrides) -> hx_train_opts:
+    o = hx_train_opts()
+    load().hx_train_opts_default(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def hx_mlp_train(net, X, T, opts: hx_train_opts, stream=None) -> dict:
+    info = hx_train_info()
+    _check(load().hx_mlp_train(net, _ptr(X), _ptr(T), X.shape[0], C.byref(opts), C.byref(info), _stream(stream)),
+           "hx_mlp_train")
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def hx_mlp_save(net, path: str):
+    _check(load().hx_mlp_save(net, path.encode()), "hx_mlp_save")
+
+
+def hx_mlp_load(path: str):
+    h = C.c_void_p()
+    _check(load().hx_mlp_load(path.encode(), C.byref(h)), "hx_mlp_load")
+    return h
+
+
+def hx_mlp_destroy(net):
+    load().hx_mlp_destroy(net)
+
+
+def hx_op_mlp_features(op, r, X, rnorm, stream=None):
+    _check(load().hx_op_mlp_features(op, _ptr(r), _ptr(X), _ptr(rnorm), _stream(stream)), "hx_op_mlp_features")
+
+
+def hx_op_mlp_targets(op, err, rnorm, T, stream=None):
+    _check(load().hx_op_mlp_targets(op, _ptr(err), _ptr(rnorm), _ptr(T), _stream(stream)), "hx_op_mlp_targets")
+
+
+def hx_op_mlp_precond(op, net, r, z, stream=None):
+    _check(load().hx_op_mlp_precond(op, net, _ptr(r), _ptr(z), _stream(stream)), "hx_op_mlp_precond")

@@ -67,6 +67,8 @@ class Problem:
 
     def solve(self, b, x=None, raise_on_error=True, **opts):
         x = self.zeros() if x is None else x
+        if "mlp" in opts and hasattr(opts["mlp"], "value"):
+            opts["mlp"] = opts["mlp"].value  # a network handle
         o = hx.hx_solve_opts_default(**opts)
         info = hx.hx_pcg_solve(self.h_op, b, x, o, raise_on_error=raise_on_error)
         return x, info

@@ -1,0 +1,188 @@
+"""GPU tests of the learned element preconditioner: network gradients and inference against the
+FP64 oracle, the element features, training, the flexible-CG solve and its fallback."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fem  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from paper_2109_04996_amd import hexpa as hx  # noqa: E402
+from paper_2109_04996_amd import learned  # noqa: E402
+from paper_2109_04996_amd.inputs import kappa_field_params, lattice_mesh  # noqa: E402
+from paper_2109_04996_amd.problem import Problem  # noqa: E402
+
+
+def _split(params, I, H, O):
+    a = 0
+    out = {}
+    for k, shape in (("W1", (H, I)), ("b1", (H,)), ("W2", (O, H)), ("b2", (O,))):
+        size = int(np.prod(shape))
+        out[k] = params[a:a + size].reshape(shape).astype(np.float64)
+        a += size
+    return out
+
+
+def _join(d):
+    return np.concatenate([d[k].ravel() for k in ("W1", "b1", "W2", "b2")]).astype(np.float32)
+
+
+@pytest.fixture
+def small_net():
+    I, H, O = 70, 33, 27  # odd sizes: partial tiles everywhere
+    net = hx.hx_mlp_create(I, H, O, 3)
+    rng = np.random.default_rng(0)
+    p = hx.hx_mlp_get_params(net)
+    p[:] = rng.uniform(-0.3, 0.3, p.size).astype(np.float32)  # non-zero biases too
+    hx.hx_mlp_set_params(net, p)
+    yield net, I, H, O
+    hx.hx_mlp_destroy(net)
+
+
+def test_gradients_match_oracle(small_net):
+    # FP32 forward/backward vs the oracle's FP64 chain rule on the same batch: <= 1e-4 relative per tensor
+    net, I, H, O = small_net
+    print("\n[case] mlp gradients", flush=True)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((131, I)).astype(np.float32)
+    T = rng.standard_normal((131, O)).astype(np.float32)
+    loss, g = hx.hx_mlp_loss_grad(net, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    prm = _split(hx.hx_mlp_get_params(net), I, H, O)
+    lo, go = omlp.loss_and_grads(prm, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    gg = _split(g, I, H, O)
+    for k in go:
+        assert np.linalg.norm(gg[k] - go[k]) <= 1e-4 * np.linalg.norm(go[k]), k
+
+
+def test_forward_fp32_and_bf16(small_net):
+    net, I, H, O = small_net
+    print("\n[case] mlp forward", flush=True)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((517, I)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Y32 = torch.empty(517, O, device="cuda")
+    Y16 = torch.empty(517, O, device="cuda")
+    hx.hx_mlp_forward(net, hx.HX_FP32, Xd, Y32)
+    hx.hx_mlp_forward(net, hx.HX_BF16, Xd, Y16)
+    prm = _split(hx.hx_mlp_get_params(net), I, H, O)
+    Yo, _ = omlp.forward(prm, X.astype(np.float64))
+    y32, y16 = Y32.cpu().numpy(), Y16.cpu().numpy()
+    assert np.linalg.norm(y32 - Yo) <= 1e-5 * np.linalg.norm(Yo)
+    # bf16 operands (2^-9 relative rounding) through two layers: about 1e-2
+    assert np.linalg.norm(y16 - Yo) <= 2e-2 * np.linalg.norm(Yo)
+
+
+def test_save_load_roundtrip(small_net, tmp_path):
+    net, I, H, O = small_net
+    path = str(tmp_path / "net.hxmlp")
+    hx.hx_mlp_save(net, path)
+    net2 = hx.hx_mlp_load(path)
+    try:
+        assert hx.hx_mlp_get_shape(net2) == (I, H, O)
+        assert np.array_equal(hx.hx_mlp_get_params(net2), hx.hx_mlp_get_params(net))
+    finally:
+        hx.hx_mlp_destroy(net2)
+
+
+def test_training_reduces_loss():
+    # learn a fixed random linear map: the loss must fall by orders of magnitude
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((2048, 16)).astype(np.float32)
+    A = rng.standard_normal((16, 8)).astype(np.float32) / 4
+    T = (X @ A).astype(np.float32)
+    net, info = learned.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), n_hidden=32, epochs=60,
+                              batch=64, lr=3e-3)
+    try:
+        assert info["final_loss"] < 0.05 * info["first_loss"], info
+    finally:
+        hx.hx_mlp_destroy(net)
+
+
+def test_element_features_and_targets():
+    p, N = 3, 3
+    kp = kappa_field_params(1000, M=64)
+    mesh = lattice_mesh(N, p, warp="B", shuffle_seed=4)
+    print("\n[case] mlp features", flush=True)
+    with Problem(N, p, p + 2, "gauss", "diffusion", mesh=mesh, kappa=kp) as pr:
+        P3 = (p + 1) ** 3
+        E = mesh["nelem"]
+        r = np.random.default_rng(5).standard_normal(mesh["nnodes"])
+        X = torch.empty(E, 2 * P3, device="cuda")
+        rn = torch.empty(E, device="cuda")
+        T = torch.empty(E, P3, device="cuda")
+        hx.hx_op_mlp_features(pr.h_op, pr.to_dev(r), X, rn)
+        err = np.random.default_rng(6).standard_normal(mesh["nnodes"])
+        hx.hx_op_mlp_targets(pr.h_op, pr.to_dev(err), rn, T)
+        X, rn, T = X.cpu().numpy(), rn.cpu().numpy(), T.cpu().numpy()
+        re = r[mesh["elem_nodes"]]
+        nrm = np.linalg.norm(re, axis=1)
+        np.testing.assert_allclose(rn, nrm, rtol=1e-6)
+        np.testing.assert_allclose(X[:, :P3], re / nrm[:, None], rtol=1e-6, atol=1e-7)
+        Xn = fem.node_coordinates(mesh, p)
+        lk = np.log(fem.kappa_eval(kp, Xn))[mesh["elem_nodes"]]
+        feat = lk - lk.mean(axis=1, keepdims=True)
+        np.testing.assert_allclose(X[:, P3:], feat, atol=1e-2 * np.abs(feat).max())  # bf16 storage
+        # targets: err_e / (|r_e| h_e^2 / mean kappa_e), h_e the mean length of the edges at corner 0
+        V = Xn[mesh["elem_nodes"]]
+        c0, c1, c2, c3 = V[:, 0], V[:, p], V[:, p * (p + 1)], V[:, p * (p + 1) ** 2]
+        h = (np.linalg.norm(c1 - c0, axis=1) + np.linalg.norm(c2 - c0, axis=1) + np.linalg.norm(c3 - c0, axis=1)) / 3
+        kbar = np.exp(lk).mean(axis=1)
+        Tr = err[mesh["elem_nodes"]] / (nrm * h * h / kbar)[:, None]
+        np.testing.assert_allclose(T, Tr, rtol=1e-5, atol=1e-6 * np.abs(Tr).max())
+
+
+@pytest.fixture(scope="module")
+def trained():
+    # small training run on two seeded coefficient fields (p = 3, 6^3 elements)
+    print("\n[case] mlp training set", flush=True)
+    X, T = learned.training_set(3, 5, "gauss", 6, seeds=(1000, 1001), rows_per_snapshot=300, kappa_M=128)
+    net, info = learned.train(X, T, epochs=60, batch=128, lr=1e-3)
+    yield net, info
+    hx.hx_mlp_destroy(net)
+
+
+def test_learned_fcg_solve_and_gain(trained):
+    net, info = trained
+    assert info["final_loss"] < info["first_loss"]
+    pr, b = learned.problem_with_kappa(6, 3, 5, "gauss", 100, kappa_M=128)  # held-out coefficient seed
+    with pr:
+        res = learned.compare_solves(pr, b, net, rtol=1e-8)
+        print("\n[learned] gain record:", res, flush=True)
+        for name, r in res.items():
+            assert r["true_rel_residual"] <= 1.05e-8, (name, r)
+        # the learned preconditioner, with or without its fallback, must finish within the
+        # fallback's own budget plus the stall window
+        lr = res["learned"]
+        assert lr["iterations"] <= res["jacobi"]["iterations"] + 40 or lr["fallback_used"] == 1
+
+
+def test_fallback_on_broken_network(trained):
+    net, _ = trained
+    pr, b = learned.problem_with_kappa(5, 3, 5, "gauss", 101, kappa_M=128)
+    with pr:
+        shape = hx.hx_mlp_get_shape(net)
+        bad = hx.hx_mlp_create(*shape, 1)
+        try:
+            # NaN weights: breakdown at the first dot product, then Jacobi PCG from x = 0
+            prm = hx.hx_mlp_get_params(bad)
+            prm[:] = np.nan
+            hx.hx_mlp_set_params(bad, prm)
+            x, info = pr.solve(b, precond=hx.HX_PC_MLP, mlp=bad.value, raise_on_error=False)
+            assert info["fallback_used"] == 1 and info["status"] == "HX_OK", info
+            assert info["true_rel_residual"] <= 1.05e-8
+            # a network that returns minus the trained correction: r'z <= 0 -> fallback
+            prm = hx.hx_mlp_get_params(net)
+            I, H, O = shape
+            s = H * (I + 1)
+            prm[s:] = -prm[s:]  # negate W2 and b2
+            hx.hx_mlp_set_params(bad, prm)
+            x, info = pr.solve(b, precond=hx.HX_PC_MLP, mlp=bad.value, fallback=hx.HX_PC_CHEBYSHEV,
+                               raise_on_error=False)
+            assert info["fallback_used"] == 1 and info["status"] == "HX_OK", info
+        finally:
+            hx.hx_mlp_destroy(bad)
