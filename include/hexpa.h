@@ -248,7 +248,10 @@ typedef struct {
   int stall_window;    /* HX_PC_MLP: stall = the residual fell by less than     */
   double stall_factor; /* stall_factor over the last stall_window iterations   */
   int mlp_mode;        /* HX_PC_MLP: 0: z = network correction; 1: z = D^-1 r plus
-                          the network correction (trained on targets e - D^-1 r) */
+                          the network correction (trained on targets e - D^-1 r);
+                          2: cheb_degree Chebyshev steps on M A e = M r with M
+                          the mode-1 map as the base (lam_max of M A from
+                          lanczos_steps power iterations; FP64 operator)        */
 } hx_solve_opts;
 
 typedef struct {
@@ -257,17 +260,20 @@ typedef struct {
   int operator_applies;  /* applies of A in any precision                    */
   double rel_residual;   /* recurrence residual at exit                      */
   double true_rel_residual; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
-  double lam_max;        /* Chebyshev: estimated lambda_max of D^-1 A         */
+  double lam_max;        /* Chebyshev: estimated lambda_max of D^-1 A (of M A
+                            for the learned Chebyshev form, mlp_mode 2)       */
   double setup_seconds;  /* Chebyshev lambda estimate, diagonal               */
   double solve_seconds;  /* wall time of the iteration                        */
   int fallback_used;     /* HX_PC_MLP: 1 if the fallback solve ran            */
   int fallback_iterations; /* iterations of the fallback solve                */
+  int fallback_reason;   /* HX_PC_MLP: 0 none, 1 breakdown (r'z <= 0, p'Ap <= 0
+                            or non-finite), 2 stall, 3 maxit                   */
 } hx_solve_info;
 
 /* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
  * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata, flexible 0, no network,
- * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 0. */
+ * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:
@@ -276,7 +282,7 @@ void hx_solve_opts_default(hx_solve_opts *opts);
  *         ignored; x is overwritten (constrained entries set to 0).
  * Synchronous: returns once x is final; the host reads 8 bytes every
  * check_every iterations. Uses work vectors owned by op (allocated on first
- * use, about 8 vectors of nnodes*ncomp doubles).
+ * use: 10 vectors of nnodes*ncomp doubles, and 10 of floats for the FP32 forms).
  * Errors: HX_EINVAL, HX_ENOCONV (maxit reached; info filled),
  * HX_EBREAKDOWN, HX_ENOMEM, HX_EHIP. */
 hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -332,14 +338,16 @@ hx_status hx_mlp_train(hx_mlp net, const float *X, const float *T, int64_t nsamp
                        hx_train_info *info, hx_stream s);
 
 /* Learned element preconditioner on a scalar diffusion operator (see the
- * HX_PC_MLP solve). For a residual r (device FP64 L-vector), element e's network
- * input is [r_e/|r_e|, log kappa_e - mean(log kappa_e)] (2 (p+1)^3 values) and the
- * correction is z = G^T (w * |r_e| h_e^2/mean(kappa_e) * net(input)), w = 1 over
- * the node's multiplicity (0 on constrained nodes), h_e the element size.
- *   hx_op_mlp_features: X [nelem][2 (p+1)^3] and rnorm [nelem] (device FP32,
- *     caller element order), the inputs for a residual r.
+ * HX_PC_MLP solve), in Jacobi-scaled variables: with D the assembled diagonal and
+ * r~ = D^-1/2 r (0 on constrained nodes), element e's network input is
+ * [r~_e/|r~_e|, f_e] (2 (p+1)^3 values), f_e = log kappa_e - mean(log kappa_e) at
+ * the element's nodes with the value 3 on constrained nodes, and the correction is
+ * z = D^-1/2 G^T (w * |r~_e| * net(input)), w = 1 over the node's multiplicity
+ * (0 on constrained nodes).
+ *   hx_op_mlp_features: X [nelem][2 (p+1)^3] and rnorm = |r~_e| [nelem] (device
+ *     FP32, caller element order), the inputs for a residual r (FP64 L-vector).
  *   hx_op_mlp_targets: T [nelem][(p+1)^3] (device FP32, caller order): the
- *     training targets err_e / (|r_e| h_e^2 / mean kappa_e) for an error vector.
+ *     training targets D^1/2 err_e / |r~_e| for an error vector err (FP64).
  *   hx_op_mlp_precond: z = the correction for r (device FP64), bf16 matrix cores.
  * Asynchronous. Errors: HX_EINVAL (shapes), HX_EUNSUPPORTED (not scalar
  * diffusion), HX_ENOMEM, HX_EHIP. */

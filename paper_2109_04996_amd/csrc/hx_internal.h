@@ -112,8 +112,8 @@ struct hx_op_s {
   // learned preconditioner: element features and work buffers (made on first use)
   bool mlp_ready = false;
   hx::DevBuf<float> mlp_logk;      // [n] log kappa at the nodes
-  hx::DevBuf<uint16_t> mlp_feat16; // [E_internal][P^3] centred log kappa, bf16
-  hx::DevBuf<float> mlp_escale;    // [E_internal] h_e^2 / mean kappa_e
+  hx::DevBuf<uint16_t> mlp_feat16; // [E_internal][P^3] centred log kappa (marker on constrained nodes), bf16
+  hx::DevBuf<float> mlp_dis;       // [n] D^-1/2 on free nodes, 0 on constrained ones
   hx::DevBuf<float> mlp_wmult;     // [n] 1 / multiplicity on free nodes, 0 on constrained ones
   hx::DevBuf<uint16_t> mlp_x16, mlp_h16;
   hx::DevBuf<float> mlp_y, mlp_rnorm;

@@ -1,16 +1,21 @@
-// Learned element-local preconditioner (not in the paper): z = G^T (w * s_e * net(x_e)).
+// Learned element-local preconditioner (not in the paper): an approximate inverse of the
+// operator's element blocks, in Jacobi-scaled variables.
 //
-// For a residual r, each element e sees the features
-//   x_e = [ r_e / |r_e| , log kappa_e - mean(log kappa_e) ]      (2 (p+1)^3 values)
-// where r_e = G_e r is the element restriction of r (libCEED section: G) and kappa_e its
-// coefficient at the element's nodes. The two-layer network maps them to a normalised
-// element correction, scaled back by s_e = |r_e| h_e^2 / mean(kappa_e) (h_e: element size);
-// the element corrections are averaged at shared nodes (w = 1/multiplicity, a partition of
-// unity) and summed with the atomic-free colored scatter G^T of the operator kernels.
-// Constrained nodes get w = 0.
+// With D the assembled diagonal and r~ = D^-1/2 r (zero on constrained nodes), element e sees
+//   x_e = [ r~_e / |r~_e| , f_e ]                                  (2 (p+1)^3 values)
+// where r~_e = G_e r~ is the element restriction (libCEED section: G) and f_e the element's
+// log kappa at its nodes minus its mean, with the marker value kConstrained on constrained
+// nodes. The network's output, scaled back by |r~_e|, is an element correction c_e in the
+// scaled variables; the corrections are averaged at shared nodes (w = 1/multiplicity, a
+// partition of unity, 0 on constrained nodes), summed with the atomic-free colored scatter
+// G^T of the operator kernels, and mapped back: z = D^-1/2 G^T (w |r~_e| net(x_e)).
+// In scaled variables the element block D_e^-1/2 A_ee D_e^-1/2 no longer depends on the size of
+// kappa or of the element, so one network serves all elements and mesh sizes; trained on
+// c_e = D_e^1/2 e_e - r~_e with e_e = A_ee^-1 r_e, z + D^-1 r is a restricted additive
+// Schwarz step over element blocks.
 //
-// Hot path: k_mlp_in (gather + norm + bf16 features), two bf16 matrix-core layers over all
-// elements (mlp.hip), k_mlp_scatter per color.
+// Hot path: k_mlp_in (gather + scale + norm + bf16 features), two bf16 matrix-core layers over
+// all elements (mlp.hip), k_mlp_scatter per color.
 #include <cmath>
 
 #include "mlp_internal.h"
@@ -20,6 +25,7 @@ namespace hx {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr float kConstrained = 3.0f;  // feature marker of a constrained node (|f| < 3 on free nodes)
 
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
   sh[threadIdx.x] = v;
@@ -48,36 +54,27 @@ __global__ void k_node_logkappa(int64_t n, const double *__restrict__ xyz, int M
   }
 }
 
-// per element (internal order): centred log kappa features (bf16) and s_e / |r_e| = h_e^2 / mean kappa
+// per element (internal order): log kappa minus its element mean, kConstrained on constrained nodes (bf16)
 __global__ void __launch_bounds__(kThreads)
-    k_elem_prep(int P, const int32_t *__restrict__ idx, const double *__restrict__ xyz, const float *__restrict__ logk,
-                uint16_t *__restrict__ feat, float *__restrict__ escale) {
+    k_elem_prep(int P, const int32_t *__restrict__ idx, const float *__restrict__ logk, const uint8_t *__restrict__ fm,
+                uint16_t *__restrict__ feat) {
   __shared__ double sh[kThreads];
   const int64_t e = blockIdx.x;
-  const int P3 = P * P * P, p = P - 1;
-  double sl = 0.0, sk = 0.0;
-  for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const float lk = logk[idx[e * P3 + l]];
-    sl += lk;
-    sk += exp((double)lk);
-  }
+  const int P3 = P * P * P;
+  double sl = 0.0;
+  for (int l = threadIdx.x; l < P3; l += kThreads) sl += logk[idx[e * P3 + l]];
   const double mean_l = block_sum_d(sl, sh) / P3;
-  const double mean_k = block_sum_d(sk, sh) / P3;
-  for (int l = threadIdx.x; l < P3; l += kThreads)
-    feat[e * P3 + l] = f32_to_bf16_bits((float)(logk[idx[e * P3 + l]] - mean_l));
-  if (threadIdx.x == 0) {
-    // element size: mean length of the three edges at the first corner
-    const int64_t c0 = idx[e * P3], c1 = idx[e * P3 + p], c2 = idx[e * P3 + p * P], c3 = idx[e * P3 + p * P * P];
-    const int64_t cs[3] = {c1, c2, c3};
-    double h = 0.0;
-    for (int i = 0; i < 3; ++i) {
-      const int64_t c = cs[i];
-      const double dx = xyz[3 * c] - xyz[3 * c0], dy = xyz[3 * c + 1] - xyz[3 * c0 + 1],
-                   dz = xyz[3 * c + 2] - xyz[3 * c0 + 2];
-      h += sqrt(dx * dx + dy * dy + dz * dz) / 3.0;
-    }
-    escale[e] = (float)(h * h / mean_k);
+  for (int l = threadIdx.x; l < P3; l += kThreads) {
+    const int64_t nd = idx[e * P3 + l];
+    feat[e * P3 + l] = f32_to_bf16_bits(fm[nd] ? (float)(logk[nd] - mean_l) : kConstrained);
   }
+}
+
+// D^-1/2 on free nodes, 0 on constrained ones
+__global__ void k_dis(int64_t n, const double *__restrict__ diag, const uint8_t *__restrict__ fm,
+                      float *__restrict__ dis) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dis[t] = (fm[t] && diag[t] > 0.0) ? (float)(1.0 / sqrt(diag[t])) : 0.f;
 }
 
 // multiplicity: colored scatter of ones (store by the first element, add by later ones)
@@ -101,40 +98,42 @@ __global__ void k_wmult(int64_t n, const uint8_t *__restrict__ fm, float *__rest
     w[t] = (fm[t] && w[t] > 0.f) ? 1.f / w[t] : 0.f;
 }
 
-// network input of each element: [r_e / |r_e|, feature] (bf16 rows, internal order) and |r_e|
+// network input of each element: [r~_e / |r~_e|, feature] (bf16 rows, internal order) and |r~_e|
 __global__ void __launch_bounds__(kThreads)
-    k_mlp_in(int P, const int32_t *__restrict__ idx, const double *__restrict__ r, const uint16_t *__restrict__ feat,
-             uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
+    k_mlp_in(int P, const int32_t *__restrict__ idx, const double *__restrict__ r, const float *__restrict__ dis,
+             const uint16_t *__restrict__ feat, uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
   __shared__ double sh[kThreads];
   const int64_t e = blockIdx.x;
   const int P3 = P * P * P;
   double s = 0.0;
   for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const double v = r[idx[e * P3 + l]];
+    const int64_t nd = idx[e * P3 + l];
+    const double v = (double)dis[nd] * r[nd];
     s += v * v;
   }
   const double nrm = sqrt(block_sum_d(s, sh));
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   uint16_t *row = X16 + e * (int64_t)(2 * P3);
   for (int l = threadIdx.x; l < P3; l += kThreads) {
-    row[l] = f32_to_bf16_bits((float)(r[idx[e * P3 + l]] * inv));
+    const int64_t nd = idx[e * P3 + l];
+    row[l] = f32_to_bf16_bits((float)((double)dis[nd] * r[nd] * inv));
     row[P3 + l] = feat[e * P3 + l];
   }
   if (threadIdx.x == 0) rnorm[e] = (float)nrm;
 }
 
-// z[node] (+)= w[node] * |r_e| * s_e * y_e[l], colored: store by the first element, add by later ones
+// z[node] (+)= D^-1/2[node] w[node] |r~_e| y_e[l], colored: store by the first element, add by later ones
 __global__ void __launch_bounds__(kThreads)
     k_mlp_scatter(int P, const int32_t *__restrict__ idx, const uint16_t *__restrict__ own,
-                  const float *__restrict__ Y, const float *__restrict__ rnorm, const float *__restrict__ escale,
+                  const float *__restrict__ Y, const float *__restrict__ rnorm, const float *__restrict__ dis,
                   const float *__restrict__ w, double *__restrict__ z, int64_t e_begin) {
   const int64_t e = e_begin + blockIdx.x;
   const int P2 = P * P, P3 = P2 * P;
-  const double sc = (double)rnorm[e] * (double)escale[e];
+  const double sc = (double)rnorm[e];
   for (int l = threadIdx.x; l < P3; l += kThreads) {
     const int k = l / P2;
     const int64_t nd = idx[e * P3 + l];
-    const double v = (double)w[nd] * sc * (double)Y[e * (int64_t)P3 + l];
+    const double v = (double)dis[nd] * (double)w[nd] * sc * (double)Y[e * (int64_t)P3 + l];
     if ((own[e * P2 + (l % P2)] >> k) & 1u)
       z[nd] = v;
     else
@@ -142,41 +141,49 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// training features in caller element order (FP32): [r_e / |r_e|, centred log kappa]; |r_e|
+// training features in caller element order (FP32): [r~_e / |r~_e|, feature]; |r~_e|
 __global__ void __launch_bounds__(kThreads)
     k_features_f32(int P, const int32_t *__restrict__ idx, const int32_t *__restrict__ order,
-                   const double *__restrict__ r, const uint16_t *__restrict__ feat, float *__restrict__ X,
-                   float *__restrict__ rnorm) {
+                   const double *__restrict__ r, const float *__restrict__ dis, const uint16_t *__restrict__ feat,
+                   float *__restrict__ X, float *__restrict__ rnorm) {
   __shared__ double sh[kThreads];
   const int64_t e = blockIdx.x;
   const int P3 = P * P * P;
   double s = 0.0;
   for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const double v = r[idx[e * P3 + l]];
+    const int64_t nd = idx[e * P3 + l];
+    const double v = (double)dis[nd] * r[nd];
     s += v * v;
   }
   const double nrm = sqrt(block_sum_d(s, sh));
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   float *row = X + (int64_t)order[e] * (2 * P3);
   for (int l = threadIdx.x; l < P3; l += kThreads) {
-    row[l] = (float)(r[idx[e * P3 + l]] * inv);
+    const int64_t nd = idx[e * P3 + l];
+    row[l] = (float)((double)dis[nd] * r[nd] * inv);
     row[P3 + l] = bf16_bits_to_f32(feat[e * P3 + l]);
   }
   if (threadIdx.x == 0) rnorm[order[e]] = (float)nrm;
 }
 
-// training targets in caller element order: err_e / (|r_e| s_e)
+// training targets in caller element order: D^1/2 err_e / |r~_e| (0 on constrained nodes)
 __global__ void __launch_bounds__(kThreads)
     k_targets_f32(int P, const int32_t *__restrict__ idx, const int32_t *__restrict__ order,
-                  const double *__restrict__ err, const float *__restrict__ rnorm, const float *__restrict__ escale,
+                  const double *__restrict__ err, const float *__restrict__ rnorm, const float *__restrict__ dis,
                   float *__restrict__ T) {
   const int64_t e = blockIdx.x;
   const int P3 = P * P * P;
   const int64_t oe = order[e];
-  const double d = (double)rnorm[oe] * (double)escale[e];
+  const double d = (double)rnorm[oe];
   const double inv = d > 0.0 ? 1.0 / d : 0.0;
-  for (int l = threadIdx.x; l < P3; l += kThreads) T[oe * P3 + l] = (float)(err[idx[e * P3 + l]] * inv);
+  for (int l = threadIdx.x; l < P3; l += kThreads) {
+    const int64_t nd = idx[e * P3 + l];
+    const double ds = (double)dis[nd];
+    T[oe * P3 + l] = ds > 0.0 ? (float)(err[nd] / ds * inv) : 0.f;
+  }
 }
+
+}  // namespace
 
 hx_status mlp_prepare(hx_op_s &op, hipStream_t s) {
   if (op.mlp_ready) return HX_OK;
@@ -192,13 +199,19 @@ hx_status mlp_prepare(hx_op_s &op, hipStream_t s) {
   }
   HX_HIP(op.mlp_logk.alloc(n));
   HX_HIP(op.mlp_feat16.alloc((size_t)E * P3));
-  HX_HIP(op.mlp_escale.alloc(E));
+  HX_HIP(op.mlp_dis.alloc(n));
   HX_HIP(op.mlp_wmult.alloc(n));
   HX_HIP(op.mlp_rnorm.alloc(E));
+  if (!op.diag_valid) {
+    if (op.diag.count < (size_t)n) HX_HIP(op.diag.alloc(n));
+    if (hx_status st = hx_op_diagonal(&op, op.diag.ptr, s)) return st;
+    op.diag_valid = true;
+  }
+  hipLaunchKernelGGL(k_dis, dim3(2048), dim3(256), 0, s, n, op.diag.ptr, m.freemask.ptr, op.mlp_dis.ptr);
   hipLaunchKernelGGL(k_node_logkappa, dim3(2048), dim3(256), 0, s, n, m.xyz.ptr, op.kappa_M, om.ptr, ph.ptr,
                      op.kappa_scale, op.kappa_shift, op.mlp_logk.ptr);
-  hipLaunchKernelGGL(k_elem_prep, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, m.xyz.ptr,
-                     op.mlp_logk.ptr, op.mlp_feat16.ptr, op.mlp_escale.ptr);
+  hipLaunchKernelGGL(k_elem_prep, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, op.mlp_logk.ptr,
+                     m.freemask.ptr, op.mlp_feat16.ptr);
   HX_HIP(hipMemsetAsync(op.mlp_wmult.ptr, 0, sizeof(float) * n, s));
   for (int c = 0; c < m.ncolors; ++c) {
     const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
@@ -213,8 +226,6 @@ hx_status mlp_prepare(hx_op_s &op, hipStream_t s) {
   return HX_OK;
 }
 
-}  // namespace
-
 hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, const double *r, double *z, hipStream_t s) {
   const int P3 = op.P * op.P * op.P;
   if (net.n_in != 2 * P3 || net.n_out != P3)
@@ -228,15 +239,15 @@ hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, const double *r, double 
     HX_HIP(op.mlp_y.alloc((size_t)E * P3));
   }
   if (op.mlp_h16.count < (size_t)(E * net.n_hid)) HX_HIP(op.mlp_h16.alloc((size_t)E * net.n_hid));
-  hipLaunchKernelGGL(k_mlp_in, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, r, op.mlp_feat16.ptr,
-                     op.mlp_x16.ptr, op.mlp_rnorm.ptr);
+  hipLaunchKernelGGL(k_mlp_in, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, r, op.mlp_dis.ptr,
+                     op.mlp_feat16.ptr, op.mlp_x16.ptr, op.mlp_rnorm.ptr);
   if (hx_status st = mlp_layers_bf16(net, op.mlp_x16.ptr, E, op.mlp_h16.ptr, op.mlp_y.ptr, s)) return st;
   if (m.nuntouched > 0) HX_HIP(hipMemsetAsync(z, 0, sizeof(double) * m.nnodes, s));
   for (int c = 0; c < m.ncolors; ++c) {
     const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
     if (e1 > e0)
       hipLaunchKernelGGL(k_mlp_scatter, dim3((unsigned)(e1 - e0)), dim3(kThreads), 0, s, op.P, m.idx.ptr, m.own.ptr,
-                         op.mlp_y.ptr, op.mlp_rnorm.ptr, op.mlp_escale.ptr, op.mlp_wmult.ptr, z, e0);
+                         op.mlp_y.ptr, op.mlp_rnorm.ptr, op.mlp_dis.ptr, op.mlp_wmult.ptr, z, e0);
   }
   HX_HIP(hipGetLastError());
   return HX_OK;
@@ -252,7 +263,7 @@ extern "C" hx_status hx_op_mlp_features(hx_op op, const double *r, float *X, flo
   if (hx_status st = mlp_prepare(*op, s)) return st;
   const hx_mesh_s &m = *op->mesh;
   hipLaunchKernelGGL(k_features_f32, dim3((unsigned)m.nelem), dim3(kThreads), 0, s, op->P, m.idx.ptr,
-                     m.order_d.ptr, r, op->mlp_feat16.ptr, X, rnorm);
+                     m.order_d.ptr, r, op->mlp_dis.ptr, op->mlp_feat16.ptr, X, rnorm);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -263,7 +274,7 @@ extern "C" hx_status hx_op_mlp_targets(hx_op op, const double *err, const float 
   if (hx_status st = mlp_prepare(*op, s)) return st;
   const hx_mesh_s &m = *op->mesh;
   hipLaunchKernelGGL(k_targets_f32, dim3((unsigned)m.nelem), dim3(kThreads), 0, s, op->P, m.idx.ptr, m.order_d.ptr,
-                     err, rnorm, op->mlp_escale.ptr, T);
+                     err, rnorm, op->mlp_dis.ptr, T);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }

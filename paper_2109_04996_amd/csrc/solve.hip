@@ -266,12 +266,34 @@ __global__ void __launch_bounds__(kVecThreads) k_convert(int64_t n, double scale
     b[t] = (TB)(scale * (double)a[t]);
 }
 
-// z = dinv r + t (Jacobi step plus a correction)
-__global__ void __launch_bounds__(kVecThreads) k_jac_plus(int64_t n, const double *__restrict__ dinv,
-                                                            const double *__restrict__ r, const double *__restrict__ t,
-                                                            double *__restrict__ z) {
+// z += dinv r (Jacobi step added to a correction already in z)
+__global__ void __launch_bounds__(kVecThreads) k_jac_add(int64_t n, const double *__restrict__ dinv,
+                                                           const double *__restrict__ r, double *__restrict__ z) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    z[i] = dinv[i] * r[i] + t[i];
+    z[i] += dinv[i] * r[i];
+}
+
+// w = m (r - w): masked residual, in place over w = A z
+__global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, const double *__restrict__ r,
+                                                          const uint8_t *__restrict__ fm, double *__restrict__ w) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = fm[i] ? r[i] - w[i] : 0.0;
+}
+
+// Chebyshev step with a general base map: d = a d + b m, z += d (k == 0: d = b m, z = d)
+__global__ void __launch_bounds__(kVecThreads) k_cheb_m(int64_t n, double a, double b, const double *__restrict__ m,
+                                                          double *__restrict__ d, double *__restrict__ z, int first) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (first) {
+      const double v = b * m[i];
+      d[i] = v;
+      z[i] = v;
+    } else {
+      const double v = a * d[i] + b * m[i];
+      d[i] = v;
+      z[i] += v;
+    }
+  }
 }
 
 // x += scale * d (FP64 x)
@@ -317,7 +339,7 @@ double tridiag_max_eig(const std::vector<double> &d, const std::vector<double> &
 
 template <typename T>
 struct Vecs {
-  T *r, *z, *p, *w, *dinv, *cd, *ct, *x, *rp;
+  T *r, *z, *p, *w, *dinv, *cd, *ct, *x, *rp, *m;
 };
 
 struct Ctx {
@@ -383,6 +405,28 @@ hx_status cheb_apply(Ctx &c, const Cheb &ch, const Vecs<T> &v, const T *r, T *z,
 // Preconditioner that is not fused into the update: computes z from r, then the partial r'z into part0.
 template <typename T>
 using PrecFn = std::function<hx_status(const T *r, T *z)>;
+
+// Chebyshev steps on M A e = M r from e = 0 with a general base map M in place of D^-1 (the same
+// recurrence as cheb_apply): z = s(M A) M r. Uses v.cd (d), v.ct (A z, then the masked residual)
+// and v.m (M of it); the FP64 operator.
+hx_status cheb_apply_base(Ctx &c, const Cheb &ch, const Vecs<double> &v, const PrecFn<double> &base, const double *r,
+                          double *z) {
+  const double theta = 0.5 * (ch.lam_hi + ch.lam_lo), delta = 0.5 * (ch.lam_hi - ch.lam_lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (hx_status st = base(r, v.m)) return st;
+  LAUNCH_V(k_cheb_m, c.n, 0.0, 1.0 / theta, v.m, v.cd, z, 1);
+  for (int k = 1; k < ch.degree; ++k) {
+    if (hx_status st = apply_T(c, z, v.ct, HX_FP64)) return st;
+    LAUNCH_V(k_mresid, c.n, r, c.op.mesh->freemask.ptr, v.ct);
+    if (hx_status st = base(v.ct, v.m)) return st;
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    LAUNCH_V(k_cheb_m, c.n, rho_new * rho, 2.0 * rho_new / delta, v.m, v.cd, z, 0);
+    rho = rho_new;
+  }
+  HX_HIP(hipGetLastError());
+  return HX_OK;
+}
 
 // PCG on vectors of type T. On entry v.r holds the masked right-hand side with r'r = rr0; solves for v.x
 // from 0. Jacobi (and none, with dinv = mask) is fused into the update kernel; other preconditioners
@@ -502,11 +546,46 @@ hx_status lanczos_lambda_max(Ctx &c, const Vecs<double> &v, int steps, double *l
   return HX_OK;
 }
 
+// Largest eigenvalue of M A for a general base map M (scalar operator), by power iteration from a
+// seeded random vector: `steps` products v <- M A v / |M A v|; the last norm ratio approaches
+// |lambda_max| from below. Uses v.p, v.w, v.z.
+hx_status power_lambda_max(Ctx &c, const Vecs<double> &v, const PrecFn<double> &base, int steps, double *lmax) {
+  std::vector<double> h(c.n);
+  std::mt19937_64 rng(12345);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  for (auto &t : h) t = U(rng);
+  HX_HIP(hipMemcpyAsync(v.p, h.data(), sizeof(double) * c.n, hipMemcpyHostToDevice, c.s));
+  LAUNCH_V((k_maskset<1>), c.n, c.op.mesh->freemask.ptr, v.p);
+  auto norm = [&](const double *a, double *out) -> hx_status {
+    LAUNCH_V((k_dot<double>), c.n, a, a, c.part0);
+    FINAL(c.part0, (const double *)nullptr, FIN_SUM, S_TMP);
+    if (hx_status st = read_scalars(c)) return st;
+    *out = std::sqrt(c.hS[S_TMP]);
+    return HX_OK;
+  };
+  double nv = 0.0, lam = 0.0;
+  if (hx_status st = norm(v.p, &nv)) return st;
+  for (int it = 0; it < steps; ++it) {
+    if (hx_status st = apply_T(c, v.p, v.w, HX_FP64)) return st;
+    LAUNCH_V((k_maskset<1>), c.n, c.op.mesh->freemask.ptr, v.w);
+    if (hx_status st = base(v.w, v.z)) return st;
+    double nz = 0.0;
+    if (hx_status st = norm(v.z, &nz)) return st;
+    if (!(nz > 0.0) || !std::isfinite(nz) || !(nv > 0.0))
+      return fail(HX_EBREAKDOWN, "power iteration for lambda_max(M A): zero or non-finite product");
+    lam = nz / nv;
+    LAUNCH_V((k_convert<double, double>), c.n, 1.0 / nz, v.z, v.p);
+    nv = 1.0;
+  }
+  *lmax = lam;
+  return HX_OK;
+}
+
 template <typename T>
 hx_status carve(DevBuf<T> &buf, int64_t n, Vecs<T> &v) {
-  if (buf.count < (size_t)(9 * n)) HX_HIP(buf.alloc((size_t)9 * n));
+  if (buf.count < (size_t)(10 * n)) HX_HIP(buf.alloc((size_t)10 * n));
   T *b = buf.ptr;
-  v = Vecs<T>{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n, b + 7 * n, b + 8 * n};
+  v = Vecs<T>{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n, b + 7 * n, b + 8 * n, b + 9 * n};
   return HX_OK;
 }
 
@@ -542,7 +621,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->fallback = HX_PC_JACOBI;
   o->stall_window = 20;
   o->stall_factor = 0.1;
-  o->mlp_mode = 0;
+  o->mlp_mode = 1;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -559,7 +638,9 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     return fail(HX_EUNSUPPORTED, "the learned preconditioner supports scalar diffusion only");
   if (mlp && o.fallback != HX_PC_JACOBI && o.fallback != HX_PC_CHEBYSHEV)
     return fail(HX_EINVAL, "fallback must be HX_PC_JACOBI or HX_PC_CHEBYSHEV");
-  if (mlp && o.mlp_mode != 0 && o.mlp_mode != 1) return fail(HX_EINVAL, "mlp_mode must be 0 or 1");
+  if (mlp && (o.mlp_mode < 0 || o.mlp_mode > 2)) return fail(HX_EINVAL, "mlp_mode must be 0, 1 or 2");
+  if (mlp && o.mlp_mode == 2 && (o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) || o.lanczos_steps < 2))
+    return fail(HX_EINVAL, "mlp_mode 2 needs cheb_degree >= 1, cheb_ratio > 1, lanczos_steps >= 2");
   if (mlp && (o.stall_window < 0 || !(o.stall_factor > 0 && o.stall_factor < 1)))
     return fail(HX_EINVAL, "stall_window >= 0 and 0 < stall_factor < 1");
   // Chebyshev runs as the preconditioner, or as the fallback of the learned one
@@ -621,6 +702,24 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     ch.lam_lo = ch.lam_hi / o.cheb_ratio;
     info->lam_max = lmax;
   }
+  // learned maps: mode 1 base M r = D^-1 r + network correction; mode 2 runs Chebyshev steps over it
+  PrecFn<double> mlp_base = [&](const double *r, double *z) -> hx_status {
+    if (hx_status st = mlp_precond_apply(*op, *o.mlp, r, z, s)) return st;
+    LAUNCH_V(k_jac_add, n, v.dinv, r, z);
+    return HX_OK;
+  };
+  Cheb chm;
+  chm.degree = o.cheb_degree;
+  if (mlp) {
+    if (hx_status st = mlp_prepare(*op, s)) return st;
+    if (o.mlp_mode == 2) {
+      double lmax = 0;
+      if (hx_status st = power_lambda_max(c, v, mlp_base, o.lanczos_steps, &lmax)) return st;
+      chm.lam_hi = 1.1 * lmax;
+      chm.lam_lo = chm.lam_hi / o.cheb_ratio;
+      info->lam_max = lmax;
+    }
+  }
   HX_HIP(hipStreamSynchronize(s));
   const auto t0 = std::chrono::steady_clock::now();
   info->setup_seconds = std::chrono::duration<double>(t0 - t_setup0).count();
@@ -675,10 +774,8 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     };
     PrecFn<double> pcm = [&](const double *r, double *z) -> hx_status {
       if (o.mlp_mode == 0) return mlp_precond_apply(*op, *o.mlp, r, z, s);
-      // Jacobi step plus the network's correction (v.ct is free outside Chebyshev)
-      if (hx_status st = mlp_precond_apply(*op, *o.mlp, r, v.ct, s)) return st;
-      LAUNCH_V(k_jac_plus, n, v.dinv, r, v.ct, z);
-      return HX_OK;
+      if (o.mlp_mode == 1) return mlp_base(r, z);
+      return cheb_apply_base(c, chm, v, mlp_base, r, z);
     };
     const PrecFn<double> *pc_cheb = cheb ? ((o.cheb_prec == HX_FP64) ? &pc64 : &pc32) : nullptr;
     const PrecFn<double> *pc = mlp ? &pcm : pc_cheb;
@@ -695,6 +792,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       // judge and fallback: Jacobi or Chebyshev PCG from the current iterate, or from the iterate
       // before the learned phase when its correction is not finite or did not lower the true residual
       info->fallback_used = 1;
+      info->fallback_reason = result == HX_EBREAKDOWN ? 1 : result == kStalled ? 2 : 3;
       double rr2 = 0;
       if (hx_status st = residual(&rr2)) return st;
       if (!std::isfinite(rr2) || rr2 >= rr) {

@@ -72,7 +72,7 @@ class hx_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int), ("operator_applies", C.c_int),
                 ("rel_residual", C.c_double), ("true_rel_residual", C.c_double), ("lam_max", C.c_double),
                 ("setup_seconds", C.c_double), ("solve_seconds", C.c_double), ("fallback_used", C.c_int),
-                ("fallback_iterations", C.c_int)]
+                ("fallback_iterations", C.c_int), ("fallback_reason", C.c_int)]
 
 
 _VP, _I64, _I32P = C.c_void_p, C.c_int64, C.c_void_p
