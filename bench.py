@@ -21,8 +21,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "GDOF/s diffusion apply p=7; time-to-1e-8 PCG solve, plain FP64 vs mixed/learned"
 COUNTERS = os.path.join(ROOT, "profiles", "bp5_p7_n48_counters.json")
-KERNEL_SOURCES = ["paper_2109_04996_amd/csrc/colloc_kernel.h", "paper_2109_04996_amd/csrc/apply_launch.h"]
-KERNEL_NAME = "hx::k_colloc<8, 1, double, double, false, true>"
+KERNEL_SOURCES = ["paper_2109_04996_amd/csrc/colloc_kernel.h", "paper_2109_04996_amd/csrc/strip_kernel.h",
+                  "paper_2109_04996_amd/csrc/apply_launch.h", "paper_2109_04996_amd/csrc/mesh.cpp"]
+KERNEL_NAME = "hx::k_colloc_strip<8, 1, double, double, 2>"  # strip scatter (degree 7, affine numbering)
+KERNEL_NAME_ELEM = "hx::k_colloc<8, 1, double, double, false, true>"  # per-element scatter
 
 
 def kernel_hash() -> str:
@@ -292,15 +294,19 @@ def main():
         for _ in range(6):
             pr.apply(x, y)
         torch.cuda.synchronize()
-        print(json.dumps(dict(pmc_run=True, kernel=KERNEL_NAME, kernel_hash=kernel_hash(), workload=f"bp5_p{p}_n{N}",
-                              copy_bytes=2 << 30, colors=pr.stats["ncolors"])), flush=True)
+        strips = pr.stats["nstrips"] > 0
+        print(json.dumps(dict(pmc_run=True, kernel=KERNEL_NAME if strips else KERNEL_NAME_ELEM,
+                              kernel_hash=kernel_hash(), workload=f"bp5_p{p}_n{N}", copy_bytes=2 << 30,
+                              launches_per_apply=pr.stats["nstrip_colors"] if strips else pr.stats["ncolors"])),
+              flush=True)
         return
     print(f"[bench] n={n} E={E} colors={pr.stats['ncolors']}; timing {a.steps} applies", file=sys.stderr, flush=True)
     total_ms, wall, per = time_applies(pr, x, y, a.steps, a.warmup)
     ms = total_ms / a.steps
     gdofs = n / (ms * 1e-3) / 1e9
     ab = algorithmic_bytes(n, E, P, Q)
-    ncol = pr.stats["ncolors"]
+    strips = pr.stats["nstrips"] > 0
+    ncol = pr.stats["nstrip_colors"] if strips else pr.stats["ncolors"]  # launches per apply
     achieved = ab["total"] / (ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(COUNTERS):
@@ -309,7 +315,7 @@ def main():
             traffic = c.get("hbm_bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=KERNEL_NAME,
+                kernel=KERNEL_NAME if strips else KERNEL_NAME_ELEM,
                 launches_per_apply=ncol, algorithmic_bytes_per_launch=round(ab["total"] / ncol),
                 avg_launch_us=round(1e3 * ms / ncol, 2), algorithmic_bytes_per_dof=round(ab["total"] / n, 2),
                 kernel_hash=kernel_hash())
@@ -319,7 +325,8 @@ def main():
                config=dict(workload=f"BP5 scalar diffusion apply, p={p}, q={Q} GLL-collocated, FP64, "
                                     f"warped unit-cube mesh A {N}^3 elements shuffled (seed 0), {n} DOFs, "
                                     f"x ~ U[-1,1] (seed 1)",
-                           N=N, p=p, q=Q, dofs=n, elements=E, colors=ncol),
+                           N=N, p=p, q=Q, dofs=n, elements=E, element_colors=pr.stats["ncolors"],
+                           strips=pr.stats["nstrips"], launches_per_apply=ncol),
                p10_ms=round(per[len(per) // 10], 4), p90_ms=round(per[(9 * len(per)) // 10], 4),
                roofline=roof)
     if a.copy_probe:

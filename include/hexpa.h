@@ -119,6 +119,10 @@ typedef struct {
   int64_t nfree;        /* nodes with dirichlet == 0                               */
   int64_t nuntouched;   /* nodes listed by no element                              */
   int64_t max_color;    /* elements in the largest color                           */
+  int64_t nstrips;      /* strips of up to 8 face-adjacent elements along r1 that
+                           the degree-7 collocated apply scatters together (0: the
+                           per-element scatter is used)                          */
+  int64_t nstrip_colors; /* strip colors (launches per apply when nstrips > 0)   */
 } hx_mesh_stats;
 
 hx_status hx_mesh_get_stats(hx_mesh mesh, hx_mesh_stats *stats);

@@ -4,11 +4,38 @@
 #include "apply_kernel.h"
 #include "colloc_kernel.h"
 #include "hx_internal.h"
+#include "strip_kernel.h"
 
 namespace hx {
 
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
+  // strips for the scalar operator (three components keep the per-element kernel: their
+  // registers would not fit the strip kernel's four waves per SIMD)
+  if constexpr (MODE == MODE_COLLOC && P == kStripP && !EOUT && NC == 1) {
+    const hx_mesh_s &m = *op.mesh;
+    if (m.nstrips > 0) {
+      // strip scatter: one launch per strip color
+      const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
+      for (int c = 0; c < m.nstrip_colors; ++c) {
+        const int64_t s0 = m.strip_color_start[c], s1 = m.strip_color_start[c + 1];
+        if (s1 <= s0) continue;
+        const dim3 grid((unsigned)(s1 - s0)), block(kStrip * 64);
+        if (m.idx_affine.ptr)
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr, qd,
+                             tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+        else if (m.idx_rows.ptr)
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 1>), grid, block, 0, s, m.idx_rows.ptr, m.strip_own.ptr, qd,
+                             tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+        else
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 0>), grid, block, 0, s, a.idx, m.strip_own.ptr, qd, tab,
+                             static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "k_colloc_strip launch");
+      return HX_OK;
+    }
+  }
   if constexpr (MODE == MODE_COLLOC && P <= 8) {
     // line-per-thread collocated kernel
     using CF = CollocCfg<P>;

@@ -12,6 +12,8 @@
 namespace hx {
 
 constexpr int kMaxP = 9;   // nodes per direction (degree 8)
+constexpr int kStrip = 8;  // elements per strip (one wavefront each) in the strip-scatter collocated kernel
+constexpr int kStripP = 8; // strips are built for this many nodes per direction (degree 7)
 constexpr int kMaxQ = 10;  // quadrature points per direction
 
 // ---------------------------------------------------------------- errors
@@ -82,11 +84,22 @@ struct hx_mesh_s {
   std::vector<double> h_xyz;         // nnodes*3
   hx::DevBuf<int32_t> idx;           // [E_internal][P^3] node ids
   hx::DevBuf<int32_t> idx_rows;      // [E_internal][P^2] first id of each r1-row (empty unless all rows are runs)
+  hx::DevBuf<int32_t> idx_affine;    // [E_internal][4] {base, s_j, s_k, 0}: node (i,j,k) = base + i + j s_j + k s_k
+                                     // (empty unless every element is numbered that way)
   hx::DevBuf<uint16_t> own;          // [E_internal][P^2] bit k: this element writes node (i,j,k) first
   hx::DevBuf<int32_t> order_d;       // internal position -> caller element id
   hx::DevBuf<double> xyz;            // nnodes*3
   hx::DevBuf<uint8_t> freemask;      // nnodes, 1 = free node
   hx::DevBuf<double> zeros;          // 64 zeros: target of masked read-modify-write loads
+  // strips: chains of up to kStrip elements, each sharing its r1 = +1 face with the next one's
+  // r1 = -1 face, scattered together by one workgroup of the collocated kernel. Strips have
+  // their own coloring (no two strips of a color share a node) and ownership bits; element ids
+  // are internal positions. Empty unless P == kStripP and the mesh has such chains.
+  int nstrip_colors = 0;
+  int64_t nstrips = 0;
+  std::vector<int64_t> strip_color_start;  // nstrip_colors + 1, in strips
+  hx::DevBuf<int32_t> strip_elems;         // [nstrips][kStrip], -1 past the strip's end
+  hx::DevBuf<uint16_t> strip_own;          // [E_internal][P^2] bit k: first write of node (i,j,k) in strip order
 };
 
 struct hx_op_s {

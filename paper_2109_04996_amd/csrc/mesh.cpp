@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <unordered_map>
 
 #include "hx_internal.h"
 
@@ -113,6 +114,144 @@ int greedy_color(int P3, int64_t nnodes, const int32_t *en, const std::vector<in
   return ncol;
 }
 
+// Strips for the strip-scatter collocated kernel (see hx_mesh_s). Element u follows t when u's
+// nodes (0, j, k) are t's nodes (p, j, k) for every (j, k): the two share t's r1 = +1 face with
+// matching in-face orientation. Chains of followers are cut into strips of at most kStrip
+// elements; the strips are colored greedily over the union of their nodes (keeping the fewer
+// colors of a Morton and a row visiting order) and ordered like the elements. Inside a strip,
+// element w > 0 does not write its r1 = -1 face (element w-1 writes the shared face after adding
+// w's part), and ownership follows the strip order. Returns false (no strips) when the chains
+// are too short to pay off or the strips need more than 64 colors.
+bool build_strips(hx_mesh_s &m, const std::vector<int32_t> &idx, const std::vector<uint64_t> &mk_int,
+                  const std::vector<int64_t> &row_key_int, std::vector<int32_t> &selems, std::vector<uint16_t> &sown,
+                  std::string &err) {
+  const int P = m.P, P2 = P * P, P3 = P2 * P, p = P - 1;
+  const int64_t E = m.nelem;
+  std::unordered_map<int32_t, std::vector<int32_t>> by_origin;
+  by_origin.reserve((size_t)E * 2);
+  for (int64_t t = 0; t < E; ++t) by_origin[idx[(size_t)t * P3]].push_back((int32_t)t);
+  std::vector<int32_t> nxt(E, -1), prv(E, -1);
+  for (int64_t t = 0; t < E; ++t) {
+    auto it = by_origin.find(idx[(size_t)t * P3 + p]);
+    if (it == by_origin.end()) continue;
+    for (int32_t u : it->second) {
+      if (u == t || prv[u] != -1) continue;
+      bool match = true;
+      for (int jk = 0; jk < P2 && match; ++jk)
+        match = idx[(size_t)u * P3 + (size_t)jk * P] == idx[(size_t)t * P3 + (size_t)jk * P + p];
+      if (match) {
+        nxt[t] = u;
+        prv[u] = (int32_t)t;
+        break;
+      }
+    }
+  }
+  std::vector<std::vector<int32_t>> strips;
+  std::vector<uint8_t> vis(E, 0);
+  auto walk = [&](int32_t t0) {
+    std::vector<int32_t> s;
+    for (int32_t u = t0; u != -1 && !vis[u]; u = nxt[u]) {
+      vis[u] = 1;
+      s.push_back(u);
+      if ((int)s.size() == hx::kStrip) {
+        strips.push_back(s);
+        s.clear();
+      }
+    }
+    if (!s.empty()) strips.push_back(s);
+  };
+  for (int64_t t = 0; t < E; ++t)
+    if (prv[t] == -1 && !vis[t]) walk((int32_t)t);
+  for (int64_t t = 0; t < E; ++t)  // closed chains (periodic meshes)
+    if (!vis[t]) walk((int32_t)t);
+  const int64_t S = (int64_t)strips.size();
+  if (S * 2 > E) return false;  // mean strip length below 2
+
+  // greedy coloring over the strips' node sets, two visiting orders
+  auto key_of = [&](int64_t s) { return strips[s][strips[s].size() / 2]; };
+  auto color_strips = [&](const std::vector<int64_t> &visit, std::vector<int> &col) {
+    col.assign(S, -1);
+    std::vector<uint64_t> used(m.nnodes, 0);
+    int ncol = 0;
+    for (int64_t s : visit) {
+      uint64_t forb = 0;
+      for (int32_t el : strips[s])
+        for (int l = 0; l < P3; ++l) forb |= used[idx[(size_t)el * P3 + l]];
+      if (~forb == 0) return 65;
+      const int c = __builtin_ctzll(~forb);
+      col[s] = c;
+      for (int32_t el : strips[s])
+        for (int l = 0; l < P3; ++l) used[idx[(size_t)el * P3 + l]] |= 1ULL << c;
+      ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+  };
+  std::vector<int64_t> v1(S), v2(S);
+  std::iota(v1.begin(), v1.end(), 0);
+  std::iota(v2.begin(), v2.end(), 0);
+  std::stable_sort(v1.begin(), v1.end(), [&](int64_t a, int64_t b) { return mk_int[key_of(a)] < mk_int[key_of(b)]; });
+  std::stable_sort(v2.begin(), v2.end(), [&](int64_t a, int64_t b) {
+    const int64_t *ka = &row_key_int[(size_t)key_of(a) * 3], *kb = &row_key_int[(size_t)key_of(b) * 3];
+    for (int d = 2; d >= 0; --d)
+      if (ka[d] != kb[d]) return ka[d] < kb[d];
+    return false;
+  });
+  std::vector<int> c1, c2;
+  const int n1 = color_strips(v1, c1), n2 = color_strips(v2, c2);
+  const std::vector<int> &col = (n2 <= n1) ? c2 : c1;
+  const int ncol = std::min(n1, n2);
+  if (ncol > 64) return false;
+  std::vector<int64_t> ord(S);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    if (col[a] != col[b]) return col[a] < col[b];
+    const uint64_t ka = mk_int[key_of(a)], kb = mk_int[key_of(b)];
+    return (col[a] & 1) ? ka > kb : ka < kb;
+  });
+  m.nstrip_colors = ncol;
+  m.nstrips = S;
+  m.strip_color_start.assign(ncol + 1, 0);
+  for (int64_t s = 0; s < S; ++s) m.strip_color_start[col[s] + 1]++;
+  for (int c = 0; c < ncol; ++c) m.strip_color_start[c + 1] += m.strip_color_start[c];
+
+  selems.assign((size_t)S * hx::kStrip, -1);
+  sown.assign((size_t)E * P2, 0);
+  std::vector<uint8_t> seen(m.nnodes, 0);
+  std::vector<int32_t> last_color(m.nnodes, -1), last_member(m.nnodes, -1);
+  std::vector<int64_t> last_strip(m.nnodes, -1);
+  for (int64_t t = 0; t < S; ++t) {
+    const auto &st = strips[ord[t]];
+    const int c = col[ord[t]];
+    for (size_t w = 0; w < st.size(); ++w) {
+      const int32_t el = st[w];
+      selems[(size_t)t * hx::kStrip + w] = el;
+      for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j)
+          for (int i = 0; i < P; ++i) {
+            const int32_t n = idx[(size_t)el * P3 + i + P * (j + P * k)];
+            if (last_color[n] == c && last_strip[n] != t) {
+              err = "strip coloring check failed: two strips of one color share a node";
+              return false;
+            }
+            // inside a strip only consecutive elements share nodes, on their common face
+            if (last_strip[n] == t && !(i == 0 && w > 0 && last_member[n] == (int32_t)w - 1)) {
+              err = "strip check failed: members other than neighbours share a node";
+              return false;
+            }
+            last_color[n] = c;
+            last_strip[n] = t;
+            last_member[n] = (int32_t)w;
+            if (w > 0 && i == 0) continue;  // written by element w-1
+            if (!seen[n]) {
+              seen[n] = 1;
+              sown[(size_t)el * P2 + j * P + i] |= (uint16_t)(1u << k);
+            }
+          }
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" hx_status hx_mesh_nodes_trilinear(int p, int64_t nelem, const int64_t *elem_verts, int64_t nverts,
@@ -198,6 +337,14 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       return false;
     });
   }
+  std::vector<int64_t> row_key(nelem * 3);
+  {
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) vol *= std::max(C.hi[d] - C.lo[d], 1e-300);
+    const double h = 0.5 * std::cbrt(vol / (double)nelem);
+    for (int64_t e = 0; e < nelem; ++e)
+      for (int d = 0; d < 3; ++d) row_key[e * 3 + d] = (int64_t)std::floor((C.c[e * 3 + d] - C.lo[d]) / h);
+  }
   std::vector<int> col1, col2;
   int n1 = greedy_color(P3, nnodes, elem_nodes, v1, col1);
   int n2 = greedy_color(P3, nnodes, elem_nodes, v2, col2);
@@ -252,6 +399,7 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
         }
   }
 
+  std::vector<int32_t> af_host;  // affine element numbering {base, s_j, s_k, 0}, empty if not affine
   // compressed restriction: one base id per row along r1 when every row of every element holds
   // consecutive ids (node (i, j, k) = base[j][k] + i); the fused kernels then read P^2 instead of
   // P^3 indices per element
@@ -274,9 +422,54 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
         delete m;
         return hx::hip_fail(e, "mesh upload");
       }
+      // affine rows: base[j][k] = base + j s_j + k s_k (a structured numbering inside each element);
+      // the kernels then compute every node id from three numbers per element
+      bool affine = P > 1;
+      std::vector<int32_t> &af = af_host;
+      af.assign((size_t)nelem * 4, 0);
+      for (int64_t t = 0; t < nelem && affine; ++t) {
+        const int32_t *r = rb.data() + (size_t)t * P2;  // [k][j]
+        const int64_t b0 = r[0], sj = (int64_t)r[1] - b0, sk = (int64_t)r[P] - b0;
+        for (int k = 0; k < P && affine; ++k)
+          for (int j = 0; j < P; ++j)
+            if ((int64_t)r[k * P + j] != b0 + j * sj + k * sk) {
+              affine = false;
+              break;
+            }
+        af[(size_t)t * 4] = (int32_t)b0;
+        af[(size_t)t * 4 + 1] = (int32_t)sj;
+        af[(size_t)t * 4 + 2] = (int32_t)sk;
+      }
+      if (!affine) af.clear();
+      if (affine) {
+        e = m->idx_affine.upload(af.data(), af.size());
+        if (e != hipSuccess) {
+          delete m;
+          return hx::hip_fail(e, "mesh upload");
+        }
+      }
     }
   }
 
+  // strips for the strip-scatter kernel (degree 7 only)
+  std::vector<int32_t> selems;
+  std::vector<uint16_t> sown;
+  bool strips = false;
+  if (P == hx::kStripP) {
+    std::vector<uint64_t> mk_int(nelem);
+    std::vector<int64_t> rk_int(nelem * 3);
+    for (int64_t t = 0; t < nelem; ++t) {
+      mk_int[t] = mk[m->order[t]];
+      for (int d = 0; d < 3; ++d) rk_int[t * 3 + d] = row_key[(int64_t)m->order[t] * 3 + d];
+    }
+    std::string serr;
+    strips = build_strips(*m, idx, mk_int, rk_int, selems, sown, serr);
+    if (!strips) {
+      m->nstrips = 0;
+      m->nstrip_colors = 0;
+      m->strip_color_start.clear();
+    }
+  }
   std::vector<uint8_t> fm(nnodes, 1);
   m->nfree = nnodes;
   if (dirichlet) {
@@ -292,7 +485,9 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       (e = m->order_d.upload(m->order.data(), m->order.size())) != hipSuccess ||
       (e = m->xyz.upload(node_xyz, (size_t)nnodes * 3)) != hipSuccess ||
       (e = m->freemask.upload(fm.data(), fm.size())) != hipSuccess ||
-      (e = m->zeros.upload(std::vector<double>(64, 0.0).data(), 64)) != hipSuccess) {
+      (e = m->zeros.upload(std::vector<double>(64, 0.0).data(), 64)) != hipSuccess ||
+      (strips && ((e = m->strip_elems.upload(selems.data(), selems.size())) != hipSuccess ||
+                  (e = m->strip_own.upload(sown.data(), sown.size())) != hipSuccess))) {
     delete m;
     return hx::hip_fail(e, "mesh upload");
   }
@@ -311,6 +506,8 @@ extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
   s->max_color = 0;
   for (int c = 0; c < m->ncolors; ++c)
     s->max_color = std::max<int64_t>(s->max_color, m->color_start[c + 1] - m->color_start[c]);
+  s->nstrips = m->nstrips;
+  s->nstrip_colors = m->nstrip_colors;
   return HX_OK;
 }
 

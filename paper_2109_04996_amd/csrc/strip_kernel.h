@@ -1,0 +1,187 @@
+// Collocated diffusion apply with a strip scatter (degree 7, P = 8 nodes per direction).
+//
+// The operator and the per-element work are those of k_colloc (colloc_kernel.h): one wavefront
+// per element, a thread per line, LDS transposes, the even-odd derivative. What changes is the
+// scatter G^T (libCEED section: G^T sums the element contributions into the L-vector). A
+// workgroup takes a strip of up to kStrip elements that follow each other along r1 (element
+// w+1's r1 = -1 face is element w's r1 = +1 face, built by the mesh), one wavefront each:
+//
+// * the shared faces are summed in LDS: element w+1 leaves its face values there, element w adds
+//   them to its own and writes the node once -- no read-modify-write and no second store;
+// * the r1-rows of a strip's elements join into rows of up to 8*7+1 consecutive nodes, written by
+//   one workgroup within its lifetime, so the partially covered memory sectors of a row are
+//   those at its two ends, not those at every element boundary;
+// * strips have their own coloring (no two strips of a color share a node), one launch per
+//   color, and their own ownership bits: the first writer of a node in strip order stores it,
+//   later writers read-modify-write it.
+//
+// Each wavefront's LDS buffers are its own, so the steps inside an element synchronise the
+// wavefront only; the face exchange is the one workgroup barrier per component.
+
+#pragma once
+
+#include "colloc_kernel.h"
+#include "hx_internal.h"
+
+namespace hx {
+
+// LDS ordering among the lanes of one wavefront: LDS operations of a wavefront complete in
+// order, so the fences only stop the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One workgroup per strip of color [s_begin, s_begin + gridDim.x); strip s's elements are
+// selems[s][0..len) (internal positions), -1 past the end. IDX: 0 one node id per element node,
+// 1 one per r1-row (ROWS of k_colloc), 2 {base, s_j, s_k} per element, read with scalar loads
+// (node (i, j, k) = base + i + j s_j + k s_k), so the gather does not wait on a vector load.
+// sown: the strip-order ownership bits of each element.
+template <int P, int NC, typename T, typename TQ, int IDX>
+__global__ void __launch_bounds__(kStrip * 64)
+    k_colloc_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
+                   const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y,
+                   const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
+  static_assert(P * P == 64, "one element per wavefront");
+  constexpr int P2 = P * P, P3 = P2 * P, LS = P + 1, PL = P * LS, BUF = P * PL;
+  __shared__ T s0[kStrip][BUF];
+  __shared__ T s1[kStrip][BUF];
+  __shared__ T face[kStrip][P2];  // element w's r1 = -1 face, [k][j]
+
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lt = tid & 63;  // w is wave-uniform
+  const int a = lt % P, b = lt / P;
+  // consecutive blocks take consecutive (spatially sorted) strips
+  const int64_t s = s_begin + blockIdx.x;
+  const int32_t *const se = selems + s * kStrip;
+  const int32_t el = se[w];
+  const bool live = el >= 0;
+  const int64_t ee = live ? el : se[0];  // a slot past the strip's end works on a valid element
+  const bool has_prev = live && w > 0;
+  const bool has_next = (w + 1 < kStrip) && se[w < kStrip - 1 ? w + 1 : w] >= 0 && live;
+  // this lane's nodes are written by the previous element of the strip
+  const bool skip = has_prev && a == 0;
+  T *const S0 = s0[w];
+  T *const S1 = s1[w];
+  const T *const C = Dg + P * P;  // even-odd coefficients
+#define AT(i, j, k) ((k) * PL + (j) * LS + (i))
+
+  int32_t nid[P];
+  if constexpr (IDX == 2) {
+    const int32_t *af = idx + ee * 4;
+    const int32_t base = af[0] + a, sj = af[1], sk = af[2];
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = base + b * sj + k * sk;
+  } else if constexpr (IDX == 1) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P2 + k * P + b) + a;
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P3 + k * P2 + b * P + a);
+  }
+  // skipped and dead lanes count as owners: their read-modify-write loads read zeros
+  const uint32_t ob = (live && !skip) ? (uint32_t)sown[ee * P2 + b * P + a] : 0xffffu;
+
+  const TQ *const qe = qd + ee * (6 * P3) + b * P + a;
+  T ga[6], gb[6];
+  auto load_plane = [&](T(&g)[6], int k) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2);
+  };
+
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    // ---- lines along r3: thread (i=a, j=b). Gather, and the r3 derivative in registers.
+    T ut[P];
+    {
+      T u[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) u[k] = x[(int64_t)nid[k] * NC + c];
+      load_plane(ga, 0);
+      load_plane(gb, 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < P; ++k) S0[AT(a, b, k)] = u[k];
+      eo_apply<P, T>(C, u, ut);
+    }
+    wave_sync();
+    // ---- read lines along r1 (thread (j=a, k=b)) and r2 (thread (i=a, k=b))
+    T li[P], lj[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      li[l] = S0[AT(l, a, b)];
+      lj[l] = S0[AT(a, l, b)];
+    }
+    wave_sync();
+    // ---- derivatives along r1 -> S0, along r2 -> S1 (same layout [k][j][i])
+    {
+      T r[P];
+      eo_apply<P, T>(C, li, r);
+#pragma unroll
+      for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+      eo_apply<P, T>(C, lj, r);
+#pragma unroll
+      for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+    }
+    wave_sync();
+    // ---- pointwise: (vr, vs, vt) = G (ur, us, ut) on lines along r3 (thread (i=a, j=b))
+    T vt[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      T(&g)[6] = (k & 1) ? gb : ga;
+      const T ur = S0[AT(a, b, k)], us = S1[AT(a, b, k)];
+      S0[AT(a, b, k)] = g[0] * ur + g[1] * us + g[2] * ut[k];
+      S1[AT(a, b, k)] = g[1] * ur + g[3] * us + g[4] * ut[k];
+      vt[k] = g[2] * ur + g[4] * us + g[5] * ut[k];
+      if (k + 2 < P) load_plane(g, k + 2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // old values of the nodes this lane read-modify-writes, requested early (no other strip of
+    // this launch touches them)
+    T old[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
+    // transposed r3 derivative in registers: yt[m] = sum_k D[k][m] vt[k]
+    T yt[P];
+    eo_apply_t<P, T>(C, vt, yt);
+    wave_sync();
+    // ---- transposed r1 derivative on S0 (thread (j=a, k=b)), r2 on S1 (thread (i=a, k=b)), in place
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      li[l] = S0[AT(l, a, b)];
+      lj[l] = S1[AT(a, l, b)];
+    }
+    {
+      T r[P];
+      eo_apply_t<P, T>(C, li, r);
+#pragma unroll
+      for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+      eo_apply_t<P, T>(C, lj, r);
+#pragma unroll
+      for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+    }
+    wave_sync();
+    // ---- element sums on lines along r3; shared faces through LDS; scatter
+    T out[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) out[k] = old[k] + (yt[k] + S0[AT(a, b, k)] + S1[AT(a, b, k)]);
+    if (skip) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) face[w][k * P + b] = out[k];
+    }
+    __syncthreads();
+    if (has_next && a == P - 1) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) out[k] += face[w + 1][k * P + b];
+    }
+    if (live && !skip) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = out[k];
+    }
+    if constexpr (NC > 1) __syncthreads();  // face[] is refilled by the next component
+  }
+#undef AT
+}
+
+}  // namespace hx

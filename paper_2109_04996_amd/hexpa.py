@@ -35,7 +35,8 @@ class HexpaError(RuntimeError):
 
 class hx_mesh_stats(C.Structure):
     _fields_ = [("p", C.c_int), ("ncolors", C.c_int), ("nelem", C.c_int64), ("nnodes", C.c_int64),
-                ("nfree", C.c_int64), ("nuntouched", C.c_int64), ("max_color", C.c_int64)]
+                ("nfree", C.c_int64), ("nuntouched", C.c_int64), ("max_color", C.c_int64),
+                ("nstrips", C.c_int64), ("nstrip_colors", C.c_int64)]
 
 
 class hx_kappa_rff(C.Structure):

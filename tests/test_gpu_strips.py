@@ -1,0 +1,118 @@
+"""GPU tests of the strip scatter of the degree-7 collocated apply.
+
+The strip kernel scatters chains of face-adjacent elements together. Its results are checked
+against the FP64 oracle on meshes whose elements have random proper rotations (so chains break
+and strips of every length from 1 to 8 occur), and at the full benchmark size against the
+E-vector path (element kernel, no scatter) summed node by node.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fem  # noqa: E402
+from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector  # noqa: E402
+from paper_2109_04996_amd.problem import Problem  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _rotations():
+    """The 24 proper rotations of the reference cube as (axis permutation, flips)."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inv = sum(1 for i in range(3) for j in range(i + 1, 3) if perm[i] > perm[j])
+        for flips in itertools.product((0, 1), repeat=3):
+            if (-1) ** inv * (-1) ** sum(flips) == 1:
+                out.append((perm, flips))
+    return out
+
+
+def rotate_elements(mesh, p, frac, seed):
+    """Renumber the local nodes and corners of a random subset of elements by a proper rotation:
+    the same hexahedra and the same assembled operator, with other local orientations."""
+    P = p + 1
+    rng = np.random.default_rng(seed)
+    E = mesh["nelem"]
+    en = mesh["elem_nodes"].reshape(E, P, P, P).copy()  # [e][k][j][i]
+    ev = mesh["elem_verts"].reshape(E, 2, 2, 2).copy()  # [e][c][b][a]
+    rots = [r for r in _rotations() if r != ((0, 1, 2), (0, 0, 0))]
+    for e in np.flatnonzero(rng.random(E) < frac):
+        perm, flips = rots[rng.integers(len(rots))]
+        for arr in (en, ev):
+            a = np.transpose(arr[e].transpose(2, 1, 0), perm)  # axes (r1, r2, r3), permuted
+            for d in range(3):
+                if flips[d]:
+                    a = np.flip(a, axis=d)
+            arr[e] = a.transpose(2, 1, 0)
+    out = dict(mesh)
+    out["elem_nodes"] = np.ascontiguousarray(en.reshape(E, P ** 3))
+    out["elem_verts"] = np.ascontiguousarray(ev.reshape(E, 8))
+    return out
+
+
+def test_strips_are_built_for_degree_7_only():
+    mesh = lattice_mesh(4, 7, warp="A", shuffle_seed=3)
+    with Problem(4, 7, 8, "gll", "diffusion", mesh=mesh) as pr:
+        assert pr.stats["nstrips"] == 16  # chains of 4 along r1
+        assert pr.stats["nstrip_colors"] >= 2
+    mesh = lattice_mesh(4, 4, warp="A", shuffle_seed=3)
+    with Problem(4, 4, 5, "gll", "diffusion", mesh=mesh) as pr:
+        assert pr.stats["nstrips"] == 0
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])  # three components run the per-element kernel on the same mesh
+def test_strip_apply_rotated_elements_matches_oracle(ncomp):
+    p, N = 7, 4
+    print(f"\n[case] strips rotated N={N} p={p} ncomp={ncomp}", flush=True)
+    mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=5), p, 0.15, seed=ncomp)
+    A = fem.assemble(mesh, p, p + 1, "gll", "diffusion")
+    with Problem(N, p, p + 1, "gll", "diffusion", ncomp=ncomp, mesh=mesh) as pr:
+        assert 0 < pr.stats["nstrips"] < mesh["nelem"]
+        x = uniform_vector(mesh["nnodes"], 7, ncomp)
+        y = pr.apply(pr.to_dev(x)).cpu().numpy()
+        yr = fem.apply(A, x, ncomp)
+        assert rel(y, yr) <= 1e-12, rel(y, yr)
+        absax = fem.apply(abs(A), np.abs(x), ncomp)
+        assert np.max(np.abs(y - yr)) <= 1e-12 * absax.max()
+        if ncomp == 1:
+            # FP32 operator with FP64 and with FP32 geometric factors through the same strips
+            from paper_2109_04996_amd import hexpa as hx
+            yr32 = fem.apply(A, x.astype(np.float32).astype(np.float64), ncomp)
+            for qp in (hx.HX_FP64, hx.HX_FP32):
+                y32 = pr.apply_f32(pr.to_dev(x, torch.float32), qp).double().cpu().numpy()
+                assert rel(y32, yr32) <= 6e-6
+
+
+def _scatter_evector(pr, ye):
+    """sum_e G_e^T y_e on the device (torch index_add_ over the caller's element nodes)."""
+    idx = torch.from_numpy(pr.mesh["elem_nodes"].astype(np.int64)).cuda().view(-1)
+    y = torch.zeros(pr.n, dtype=torch.float64, device="cuda")
+    y.index_add_(0, idx, ye.reshape(-1))
+    return y
+
+
+@pytest.mark.parametrize("N,frac", [(9, 0.0), (9, 0.2), (48, 0.0)])
+def test_strip_apply_matches_evector_sum(N, frac):
+    # N = 9: chains of 9 cut into 8 + 1; N = 48: the benchmark mesh (6 strips of 8 per chain)
+    p = 7
+    print(f"\n[case] strips vs E-vector N={N} frac={frac}", flush=True)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    if frac > 0:
+        mesh = rotate_elements(mesh, p, frac, seed=11)
+    with Problem(N, p, p + 1, "gll", "diffusion", mesh=mesh) as pr:
+        assert pr.stats["nstrips"] > 0
+        x = pr.to_dev(uniform_vector(mesh["nnodes"], 1))
+        y = pr.apply(x)
+        ye = pr.apply_elem(x)
+        yref = _scatter_evector(pr, ye)
+        err = float(torch.linalg.norm(y - yref) / torch.linalg.norm(yref))
+        assert err <= 1e-13, err
+        # the strip path is deterministic
+        assert torch.equal(y, pr.apply(x))
