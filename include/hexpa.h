@@ -239,8 +239,12 @@ typedef struct {
   int cheb_prec;       /* operator precision in the Chebyshev polynomial:
                           HX_FP64, HX_FP32 or HX_BF16                          */
   int lanczos_steps;   /* steps of the lam_max estimate (>= 2)               */
-  double inner_rtol;   /* IR: inner FP32 solve tolerance                      */
-  int inner_maxit;     /* IR: inner iteration cap per outer step              */
+  double inner_rtol;   /* IR: inner FP32 solve tolerance (relative to the outer
+                          residual; loosened to 0.5 rtol ||b|| / ||r|| when that
+                          is larger, at most 0.5)                              */
+  int inner_maxit;     /* IR: inner iteration cap per outer step (a restart
+                          loses the Krylov space: keep it above the iterations
+                          one inner solve needs)                               */
   int inner_qdata;     /* IR: HX_FP64 or HX_FP32 geometric factors            */
   int flexible;        /* 1: flexible CG (Polak-Ribiere beta) for preconditioners
                           that are not exactly linear or symmetric (HX_BF16
@@ -276,7 +280,7 @@ typedef struct {
 
 /* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
- * inner_rtol 1e-4, inner_maxit 200, FP64 inner qdata, flexible 0, no network,
+ * inner_rtol 1e-4, inner_maxit 10000, FP64 inner qdata, flexible 0, no network,
  * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 

@@ -1,8 +1,11 @@
 // Host-side launch of the fused apply: one launch per element color, in color order.
 #pragma once
 
+#include <type_traits>
+
 #include "apply_kernel.h"
 #include "colloc_kernel.h"
+#include "gauss_kernel.h"
 #include "hx_internal.h"
 #include "strip_kernel.h"
 
@@ -56,6 +59,24 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_colloc launch");
+    return HX_OK;
+  }
+  // line-per-thread interpolating kernel, one element per wavefront: FP64 diffusion (one
+  // component) and FP64 mass with q >= 7, where it beats the point-per-thread kernel; in FP32,
+  // and for mass at smaller q, that kernel fills its wavefronts with several elements and wins
+  constexpr bool kGauss = std::is_same<T, double>::value && Q <= 8 && !EOUT &&
+                          ((MODE == MODE_DIFF && NC == 1 && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+  if constexpr (kGauss) {
+    const hx_mesh_s &m = *op.mesh;
+    const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
+    for (int c = 0; c < m.ncolors; ++c) {
+      const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
+      if (e1 <= e0) continue;
+      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)(e1 - e0)), dim3(64), 0, s, a.idx, a.own, qd,
+                         tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_gauss launch");
     return HX_OK;
   }
   constexpr int EPB = EpbOf<Q>::v;

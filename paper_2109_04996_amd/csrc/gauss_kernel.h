@@ -1,0 +1,311 @@
+// Fused apply with an interpolation step (Gauss points, BP1-BP4) for q <= 8, line per thread.
+//
+// Same operator as MODE_DIFF / MODE_MASS of apply_kernel.h (Benchmarks section: tensor-product
+// sum factorization; libCEED section: G^T B^T D B G in one pass), organised like the collocated
+// kernel (colloc_kernel.h): one wavefront per element, every 1D contraction on a whole line held
+// in one thread's registers, lines moving between the three directions through padded LDS
+// buffers, the 1D tables read with wave-uniform (scalar) loads, branch-free global loads and
+// the pointwise data streamed two planes ahead.
+//
+// Diffusion, thread (a, b) of the Q x Q tile:
+//   interpolate x along r3 in registers (thread (i, j), P -> Q), then along r2 (thread (i, qk))
+//   and r1 (thread (qj, qk)) through LDS; differentiate along r1 in registers, along r3 and r2
+//   through LDS; pointwise on lines along r3 (thread (qi, qj)); the transposed derivatives; the
+//   transposed interpolations along r1, r2 and last r3 in registers, which leaves thread (i, j)
+//   with the line of node values (i, j, 0..P-1) that the colored scatter writes.
+// Mass: interpolate, scale on lines along r1 (thread (qj, qk), where the pointwise data of a line
+// is contiguous), then the transposed interpolations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "apply_kernel.h"
+#include "colloc_kernel.h"
+
+namespace hx {
+
+// y[q] = sum_i B[q][i] u[i] (B row-major [Q][P], wave-uniform table)
+template <int P, int Q, typename T>
+__device__ __forceinline__ void interp_fwd(const T *__restrict__ B0, const T (&u)[P], T (&y)[Q]) {
+  const const_ptr<T> B = launder_uniform(B0);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) s += B[q * P + i] * u[i];
+    y[q] = s;
+  }
+}
+
+// y[i] = sum_q B[q][i] v[q]
+template <int P, int Q, typename T>
+__device__ __forceinline__ void interp_bwd(const T *__restrict__ B0, const T (&v)[Q], T (&y)[P]) {
+  const const_ptr<T> B = launder_uniform(B0);
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += B[q * P + i] * v[q];
+    y[i] = s;
+  }
+}
+
+// y = D u and y = D^T v for the Q x Q collocated derivative on the q points (row-major [Q][Q])
+template <int Q, typename T>
+__device__ __forceinline__ void deriv_fwd(const T *__restrict__ D0, const T (&u)[Q], T (&y)[Q]) {
+  const const_ptr<T> D = launder_uniform(D0);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    T s = 0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) s += D[q * Q + l] * u[l];
+    y[q] = s;
+  }
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void deriv_bwd(const T *__restrict__ D0, const T (&v)[Q], T (&y)[Q]) {
+  const const_ptr<T> D = launder_uniform(D0);
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += D[q * Q + m] * v[q];
+    y[m] = s;
+  }
+}
+
+__device__ __forceinline__ void wave_sync_g() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One element per wavefront (a workgroup is one wavefront). tab: interp [Q][P] then D [Q][Q].
+template <int P, int Q, int MODE, int NC, typename T, typename TQ>
+__global__ void __launch_bounds__(64)
+    k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
+            const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
+            const T *__restrict__ zero) {
+  static_assert(Q * Q <= 64 && P <= Q, "one element per wavefront, q >= p+1");
+  static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+  constexpr int LS = Q + 1, PL = Q * LS, BUF = Q * PL;
+  constexpr int NCQ = (MODE == MODE_MASS) ? 1 : 6;
+  __shared__ T S0[BUF];
+  __shared__ T S1[BUF];
+#define AT(i, j, k) ((k) * PL + (j) * LS + (i))
+
+  const int lt0 = threadIdx.x;
+  const bool lane_live = lt0 < Q2;
+  const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
+  const int a = lt % Q, b = lt / Q;
+  const int64_t e = e_begin + blockIdx.x;  // grid = e_end - e_begin
+  const T *const tI = tab;
+  const T *const tD = tab + Q * P;
+  // node lanes: (i, j) = (a, b) for a, b < P; the others address node (min(a, P-1), min(b, P-1))
+  const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
+  const bool node_lane = lane_live && a < P && b < P;
+
+  int32_t nid[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+  const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
+
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    // ---- interpolate along r3 in registers: thread (i, j), S0[i][j][qk]
+    {
+      T u[P], uq[Q];
+#pragma unroll
+      for (int k = 0; k < P; ++k) u[k] = x[(int64_t)nid[k] * NC + c];
+      interp_fwd<P, Q, T>(tI, u, uq);
+      if (node_lane) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) S0[AT(a, b, q)] = uq[q];
+      }
+    }
+    wave_sync_g();
+    // ---- along r2: thread (i = a < P, qk = b), S1[i][qj][qk]
+    {
+      T u[P], uq[Q];
+#pragma unroll
+      for (int j = 0; j < P; ++j) u[j] = S0[AT(an, j, b)];
+      interp_fwd<P, Q, T>(tI, u, uq);
+      if (lane_live && a < P) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) S1[AT(a, q, b)] = uq[q];
+      }
+    }
+    wave_sync_g();
+    // ---- along r1: thread (qj = a, qk = b) holds the line of u at (0..Q-1, a, b)
+    T ul[Q];
+    {
+      T u[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) u[i] = S1[AT(i, a, b)];
+      interp_fwd<P, Q, T>(tI, u, ul);
+    }
+    T w[Q];  // the field after the pointwise step and the transposed derivatives, on r3 lines of (a, b)
+    if constexpr (MODE == MODE_MASS) {
+      // pointwise on the r1 line: qdata (qi, qj=a, qk=b) is contiguous in qi
+      const TQ *const ql = qd + e * Q3 + b * Q2 + a * Q;
+      T v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = ul[q] * (T)__builtin_nontemporal_load(ql + q);
+      // transposed interpolation along r1 straight from registers: S0[i][qj][qk]
+      T z[P];
+      interp_bwd<P, Q, T>(tI, v, z);
+      wave_sync_g();
+      if (lane_live) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = z[i];
+      }
+      (void)w;
+    } else {
+      // r1 derivative in registers; u to S0 (for the r3 and r2 lines) and ur to S1 (the r1
+      // interpolation above was the last reader of S1)
+      {
+        T ur[Q];
+        deriv_fwd<Q, T>(tD, ul, ur);
+        wave_sync_g();
+        if (lane_live) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            S0[AT(q, a, b)] = ul[q];
+            S1[AT(q, a, b)] = ur[q];
+          }
+        }
+      }
+      wave_sync_g();
+      // r3 derivative on the r3 line of (qi = a, qj = b), kept in registers; r2 derivative on the
+      // r2 line of (qi = a, qk = b), to S0 once every lane has read u
+      T ut[Q];
+      {
+        T lk[Q];
+#pragma unroll
+        for (int l = 0; l < Q; ++l) lk[l] = S0[AT(a, b, l)];
+        deriv_fwd<Q, T>(tD, lk, ut);
+      }
+      {
+        T lj[Q], us[Q];
+#pragma unroll
+        for (int l = 0; l < Q; ++l) lj[l] = S0[AT(a, l, b)];
+        deriv_fwd<Q, T>(tD, lj, us);
+        wave_sync_g();
+        if (lane_live) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) S0[AT(a, q, b)] = us[q];
+        }
+      }
+      // plane-ahead pointwise data (planes along r3 of the (qi = a, qj = b) column)
+      const TQ *const qe = qd + e * (6 * Q3) + b * Q + a;
+      T ga[6], gb[6];
+      auto load_plane = [&](T(&g)[6], int k) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * Q2);
+      };
+      load_plane(ga, 0);
+      load_plane(gb, 1);
+      wave_sync_g();
+      // pointwise on r3 lines: thread (qi = a, qj = b); S1 holds ur, S0 us; vr -> S1, vs -> S0
+      T vt[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        T(&g)[6] = (k & 1) ? gb : ga;
+        const T r = S1[AT(a, b, k)], s = S0[AT(a, b, k)];
+        const T t = ut[k];
+        if (lane_live) {
+          S1[AT(a, b, k)] = g[0] * r + g[1] * s + g[2] * t;
+          S0[AT(a, b, k)] = g[1] * r + g[3] * s + g[4] * t;
+        }
+        vt[k] = g[2] * r + g[4] * s + g[5] * t;
+        if (k + 2 < Q) load_plane(g, k + 2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      deriv_bwd<Q, T>(tD, vt, w);  // r3 part, on the r3 line of (a, b)
+      wave_sync_g();
+      // transposed r1 (thread (qj = a, qk = b), from S1) and r2 (thread (qi = a, qk = b), from S0)
+      {
+        T ri[Q], rj[Q];
+        {
+          T li[Q];
+#pragma unroll
+          for (int l = 0; l < Q; ++l) li[l] = S1[AT(l, a, b)];
+          deriv_bwd<Q, T>(tD, li, ri);
+        }
+        {
+          T lj[Q];
+#pragma unroll
+          for (int l = 0; l < Q; ++l) lj[l] = S0[AT(a, l, b)];
+          deriv_bwd<Q, T>(tD, lj, rj);
+        }
+        wave_sync_g();
+        if (lane_live) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            S1[AT(q, a, b)] = ri[q];
+            S0[AT(a, q, b)] = rj[q];
+          }
+        }
+      }
+      wave_sync_g();
+      // sum of the three parts on r3 lines, to S0 for the transposed interpolations
+#pragma unroll
+      for (int k = 0; k < Q; ++k) w[k] += S0[AT(a, b, k)] + S1[AT(a, b, k)];
+      wave_sync_g();
+      if (lane_live) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) S0[AT(a, b, k)] = w[k];
+      }
+      wave_sync_g();
+      // transposed interpolation along r1: thread (qj = a, qk = b), S0[i][qj][qk]
+      {
+        T v[Q], z[P];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = S0[AT(q, a, b)];
+        interp_bwd<P, Q, T>(tI, v, z);
+        wave_sync_g();
+        if (lane_live) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = z[i];
+        }
+      }
+    }
+    wave_sync_g();
+    // ---- transposed interpolation along r2: thread (i = a < P, qk = b), S1[i][j][qk]
+    {
+      T v[Q], z[P];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = S0[AT(an, q, b)];
+      interp_bwd<P, Q, T>(tI, v, z);
+      if (lane_live && a < P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = z[j];
+      }
+    }
+    // old values of the nodes this lane read-modify-writes (no other element of this launch
+    // touches them), requested before the last contraction
+    T old[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
+    wave_sync_g();
+    // ---- transposed interpolation along r3 in registers: thread (i, j) -> node line (i, j, 0..P-1)
+    {
+      T v[Q], z[P];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = S1[AT(an, bn, q)];
+      interp_bwd<P, Q, T>(tI, v, z);
+      if (node_lane) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
+      }
+    }
+    if constexpr (NC > 1) wave_sync_g();
+  }
+#undef AT
+}
+
+}  // namespace hx

@@ -614,7 +614,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->cheb_prec = HX_FP32;
   o->lanczos_steps = 20;
   o->inner_rtol = 1e-4;
-  o->inner_maxit = 200;
+  o->inner_maxit = 10000;
   o->inner_qdata = HX_FP64;
   o->flexible = 0;
   o->mlp = nullptr;
@@ -829,7 +829,10 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       int it = 0;
       double rri = 0;
       // inner r'r starts at ~1 (the residual is normalised)
-      hx_status st = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, cg_prec, 1.0, o.inner_rtol * o.inner_rtol,
+      // inner target: inner_rtol, loosened on the last steps to what the outer tolerance still needs
+      // (half of rtol ||b|| / ||r||), and at least a halving
+      const double inner_rel = std::min(0.5, std::max(o.inner_rtol, 0.5 * o.rtol * bn / rn));
+      hx_status st = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, cg_prec, 1.0, inner_rel * inner_rel,
                                      o.inner_maxit, std::min(o.check_every, o.inner_maxit), o.flexible != 0, &it, &rri);
       if (st == HX_EBREAKDOWN && it > 1) st = HX_OK;  // keep the partial correction; the FP64 residual judges it
       if (st) return st;
