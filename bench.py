@@ -230,6 +230,66 @@ def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 100
     return out
 
 
+SWEEP = [  # (label, kind, rule, p, q, ncomp, N list)
+    ("BP5", "diffusion", "gll", 7, 8, 1, (15, 20, 28, 36, 44, 48)),
+    ("BP5", "diffusion", "gll", 4, 5, 1, (25, 45, 65, 85)),
+    ("BP5", "diffusion", "gll", 2, 3, 1, (50, 110, 170)),
+    ("BP1", "mass", "gauss", 7, 9, 1, (48,)),
+    ("BP1", "mass", "gauss", 4, 6, 1, (85,)),
+    ("BP1", "mass", "gauss", 2, 4, 1, (170,)),
+    ("BP3", "diffusion", "gauss", 6, 8, 1, (48,)),
+    ("BP3", "diffusion", "gauss", 7, 9, 1, (48,)),
+    ("BP4", "diffusion", "gauss", 7, 9, 3, (32,)),
+    ("BP6", "diffusion", "gll", 7, 8, 3, (32,)),
+]
+
+
+def sweep(steps=20, warmup=3):
+    """Apply throughput over the survey's size sweep and the other operator kinds: one JSON line per
+    case (FP64 operator; FP32-operator figures beside it)."""
+    import torch
+
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
+    from paper_2109_04996_amd.problem import Problem
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for label, kind, rule, p, q, nc, Ns in SWEEP:
+        for N in Ns:
+            print(f"[bench] sweep {label} p={p} q={q} ncomp={nc} N={N}", file=sys.stderr, flush=True)
+            mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+            pr = Problem(N, p, q, rule, kind, ncomp=nc, mesh=mesh)
+            n = mesh["nnodes"]
+            x = pr.to_dev(uniform_vector(n, 1, nc))
+            y = pr.zeros()
+            x32, y32 = x.float(), torch.zeros(pr.n, dtype=torch.float32, device="cuda")
+            ms = timed(lambda: pr.apply(x, y))
+            ms32 = timed(lambda: hx.hx_op_apply_f32(pr.h_op, hx.HX_FP32, x32, y32))
+            ab = algorithmic_bytes(n, mesh["nelem"], p + 1, q, 1 if kind == "mass" else 6, nc)
+            dofs = n * nc
+            print(json.dumps(dict(sweep=label, kind=kind, rule=rule, p=p, q=q, ncomp=nc, N=N, dofs=dofs,
+                                  fp64_ms=round(ms, 4), fp64_gdofs=round(dofs / ms / 1e6, 2),
+                                  algorithmic_bytes_per_dof=round(ab["total"] / dofs, 1),
+                                  roofline_frac=round(ab["total"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                                  fp32_q32_ms=round(ms32, 4), fp32_q32_gdofs=round(dofs / ms32 / 1e6, 2),
+                                  cache_assisted=bool(ab["total"] < 1.5e9), strips=pr.stats["nstrips"])),
+                  flush=True)
+            pr.close()
+            del x, y, x32, y32
+            torch.cuda.empty_cache()
+
+
 def cpu_baseline(p: int, budget_s: float = 20.0):
     """The oracle (scipy CSR SpMV of the assembled matrix) on a bounded sample of the same workload."""
     import numpy as np
@@ -267,6 +327,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--all", action="store_true",
                     help="also run the vector-IR, variable-coefficient Chebyshev and learned-preconditioner suites")
+    ap.add_argument("--sweep", action="store_true",
+                    help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
     a = ap.parse_args()
@@ -283,6 +345,9 @@ def main():
 
     hx.load()
     torch.cuda.set_device(0)
+    if a.sweep:
+        sweep()
+        return
     N, p = a.N, a.p
     P = Q = p + 1
     print(f"[bench] building BP5 mesh N={N} p={p}", file=sys.stderr, flush=True)

@@ -55,13 +55,22 @@ struct TabLayout {
   static constexpr int size = (MODE == MODE_COLLOC) ? P * P : Q * P + Q * Q;
 };
 
+// Work item of block bid in a launch of G blocks. The hardware deals consecutive blocks
+// round-robin to the 8 XCDs; item = the block's place in a contiguous run per XCD, so consecutive
+// items -- the components of one element, then spatially neighbouring elements -- share an XCD
+// and its L2.
+__device__ __forceinline__ int xcd_item(int bid, int G) {
+  const int xcd = bid & 7, loc = bid >> 3, base = G >> 3, rem = G & 7;
+  return xcd * base + (xcd < rem ? xcd : rem) + loc;
+}
+
 template <typename TQ, typename T>
 __device__ __forceinline__ T ld_q(const TQ *p) {
   return static_cast<T>(__builtin_nontemporal_load(p));
 }
 
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
-__global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
+__global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_waves_per_eu(2)))
     k_apply(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
             const int32_t *__restrict__ order, int64_t e_begin, int64_t e_end) {
@@ -75,11 +84,9 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
   const int tid = threadIdx.x;
   for (int t = tid; t < TL::size; t += EPB * Q2) s_tab[t] = tab[t];
 
-  // XCD-aware block order: hardware deals consecutive blocks round-robin to the
-  // 8 XCDs; give each XCD a contiguous run of (spatially sorted) elements.
-  const int G = gridDim.x, bid = blockIdx.x;
-  const int xcd = bid & 7, loc = bid >> 3, base = G >> 3, rem = G & 7;
-  const int eb = xcd * base + (xcd < rem ? xcd : rem) + loc;
+  // one component of EPB elements per block; XCD-aware order (components of a block adjacent)
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int eb = item / NC, c = item - eb * NC;
   const int slot = tid / Q2, lt = tid - slot * Q2;
   const int a = lt % Q, b = lt / Q;
   const int64_t e = e_begin + (int64_t)eb * EPB + slot;
@@ -101,8 +108,7 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
   const TQ *qe = qd + e * (int64_t)(NCQ * Q3) + b * Q + a;
   __syncthreads();
 
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
+  {
     T yv[P];
     if constexpr (MODE == MODE_COLLOC) {
       T u[P];
@@ -275,7 +281,6 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q)
         for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + yv[k];
       }
     }
-    if constexpr (NC > 1) __syncthreads();
   }
 }
 

@@ -13,9 +13,8 @@ namespace hx {
 
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
-  // strips for the scalar operator (three components keep the per-element kernel: their
-  // registers would not fit the strip kernel's four waves per SIMD)
-  if constexpr (MODE == MODE_COLLOC && P == kStripP && !EOUT && NC == 1) {
+  // strips (one workgroup per strip and component)
+  if constexpr (MODE == MODE_COLLOC && P == kStripP && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
     if (m.nstrips > 0) {
       // strip scatter: one launch per strip color
@@ -23,7 +22,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
       for (int c = 0; c < m.nstrip_colors; ++c) {
         const int64_t s0 = m.strip_color_start[c], s1 = m.strip_color_start[c + 1];
         if (s1 <= s0) continue;
-        const dim3 grid((unsigned)(s1 - s0)), block(kStrip * 64);
+        const dim3 grid((unsigned)((s1 - s0) * NC)), block(kStrip * 64);
         if (m.idx_affine.ptr)
           hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr, qd,
                              tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
@@ -47,7 +46,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
-      const int64_t nb = (e1 - e0 + CF::EPB - 1) / CF::EPB;
+      const int64_t nb = (e1 - e0 + CF::EPB - 1) / CF::EPB * NC;  // blocks: element groups x components
       if (m.idx_rows.ptr)
         hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, true>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
                            m.idx_rows.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
@@ -65,14 +64,14 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // component) and FP64 mass with q >= 7, where it beats the point-per-thread kernel; in FP32,
   // and for mass at smaller q, that kernel fills its wavefronts with several elements and wins
   constexpr bool kGauss = std::is_same<T, double>::value && Q <= 8 && !EOUT &&
-                          ((MODE == MODE_DIFF && NC == 1 && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+                          ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
   if constexpr (kGauss) {
     const hx_mesh_s &m = *op.mesh;
     const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
-      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)(e1 - e0)), dim3(64), 0, s, a.idx, a.own, qd,
+      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)((e1 - e0) * NC)), dim3(64), 0, s, a.idx, a.own, qd,
                          tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero);
     }
     hipError_t e = hipGetLastError();
@@ -84,7 +83,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   for (int c = 0; c < m.ncolors; ++c) {
     const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
     if (e1 <= e0) continue;
-    const int64_t nb = (e1 - e0 + EPB - 1) / EPB;
+    const int64_t nb = (e1 - e0 + EPB - 1) / EPB * NC;  // blocks: element groups x components
     hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s, a.idx,
                        a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1);
   }

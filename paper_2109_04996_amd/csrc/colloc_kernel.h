@@ -148,11 +148,11 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS)
   __shared__ T s1[EPB][CF::BUF];
 
   const int tid = threadIdx.x;
-  // XCD-aware block order: hardware deals consecutive blocks round-robin to the 8 XCDs;
-  // give each XCD a contiguous run of (spatially sorted) elements.
+  // one component of EPB elements per block, XCD-aware order (components of a block adjacent)
   const int G = gridDim.x, bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3, base = G >> 3, rem = G & 7;
-  const int eb = xcd * base + (xcd < rem ? xcd : rem) + loc;
+  const int item = xcd * base + (xcd < rem ? xcd : rem) + loc;
+  const int eb = item / NC, c = item - eb * NC;
   const int slot = tid / P2, lt = tid - slot * P2;
   const int a = lt % P, b = lt / P;
   const int64_t e_first = e_begin + (int64_t)eb * EPB;  // first element of this workgroup (always valid)
@@ -184,8 +184,7 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS)
     for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2);
   };
 
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
+  {
     // ---- lines along r3: thread (i=a, j=b). Gather, and the r3 derivative in registers.
     T ut[P];
     {
@@ -269,7 +268,6 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS)
           y[(int64_t)nid[k] * NC + c] = old[k] + (yt[k] + S0[AT(a, b, k)] + S1[AT(a, b, k)]);
       }
     }
-    if constexpr (NC > 1) __syncthreads();
   }
 #undef AT
 }

@@ -102,7 +102,12 @@ __global__ void __launch_bounds__(64)
   const bool lane_live = lt0 < Q2;
   const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
   const int a = lt % Q, b = lt / Q;
-  const int64_t e = e_begin + blockIdx.x;  // grid = e_end - e_begin
+  // one component of one element per block (grid = (e_end - e_begin) NC); with several
+  // components, an XCD-aware order keeps an element's components on one XCD
+  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int64_t eo = item / NC;
+  const int c = item - (int)eo * NC;
+  const int64_t e = e_begin + eo;
   const T *const tI = tab;
   const T *const tD = tab + Q * P;
   // node lanes: (i, j) = (a, b) for a, b < P; the others address node (min(a, P-1), min(b, P-1))
@@ -114,8 +119,7 @@ __global__ void __launch_bounds__(64)
   for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
   const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
 
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
+  {
     // ---- interpolate along r3 in registers: thread (i, j), S0[i][j][qk]
     {
       T u[P], uq[Q];
@@ -303,7 +307,6 @@ __global__ void __launch_bounds__(64)
         for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
       }
     }
-    if constexpr (NC > 1) wave_sync_g();
   }
 #undef AT
 }

@@ -33,7 +33,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One workgroup per strip of color [s_begin, s_begin + gridDim.x); strip s's elements are
+// One workgroup per (strip, component) of color [s_begin, s_begin + gridDim.x / NC); strip s's elements are
 // selems[s][0..len) (internal positions), -1 past the end. IDX: 0 one node id per element node,
 // 1 one per r1-row (ROWS of k_colloc), 2 {base, s_j, s_k} per element, read with scalar loads
 // (node (i, j, k) = base + i + j s_j + k s_k), so the gather does not wait on a vector load.
@@ -52,8 +52,11 @@ __global__ void __launch_bounds__(kStrip * 64)
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lt = tid & 63;  // w is wave-uniform
   const int a = lt % P, b = lt / P;
-  // consecutive blocks take consecutive (spatially sorted) strips
-  const int64_t s = s_begin + blockIdx.x;
+  // one component of one strip per block: consecutive blocks take consecutive (spatially sorted)
+  // strips; with several components, an XCD-aware order keeps a strip's components on one XCD
+  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int sl = item / NC, c = item - sl * NC;
+  const int64_t s = s_begin + sl;
   const int32_t *const se = selems + s * kStrip;
   const int32_t el = se[w];
   const bool live = el >= 0;
@@ -90,8 +93,7 @@ __global__ void __launch_bounds__(kStrip * 64)
     for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2);
   };
 
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
+  {
     // ---- lines along r3: thread (i=a, j=b). Gather, and the r3 derivative in registers.
     T ut[P];
     {
@@ -179,7 +181,6 @@ __global__ void __launch_bounds__(kStrip * 64)
 #pragma unroll
       for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = out[k];
     }
-    if constexpr (NC > 1) __syncthreads();  // face[] is refilled by the next component
   }
 #undef AT
 }
