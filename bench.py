@@ -239,6 +239,7 @@ SWEEP = [  # (label, kind, rule, p, q, ncomp, N list)
     ("BP1", "mass", "gauss", 2, 4, 1, (170,)),
     ("BP3", "diffusion", "gauss", 6, 8, 1, (48,)),
     ("BP3", "diffusion", "gauss", 7, 9, 1, (48,)),
+    ("BP2", "mass", "gauss", 7, 9, 3, (32,)),
     ("BP4", "diffusion", "gauss", 7, 9, 3, (32,)),
     ("BP6", "diffusion", "gll", 7, 8, 3, (32,)),
 ]

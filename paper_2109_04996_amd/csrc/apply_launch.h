@@ -60,10 +60,10 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     if (e != hipSuccess) return hip_fail(e, "k_colloc launch");
     return HX_OK;
   }
-  // line-per-thread interpolating kernel, one element per wavefront: FP64 diffusion (one
-  // component) and FP64 mass with q >= 7, where it beats the point-per-thread kernel; in FP32,
-  // and for mass at smaller q, that kernel fills its wavefronts with several elements and wins
-  constexpr bool kGauss = std::is_same<T, double>::value && Q <= 8 && !EOUT &&
+  // line-per-thread interpolating kernel, one element per workgroup: FP64 diffusion and FP64 mass
+  // with q >= 7, where it beats the point-per-thread kernel; in FP32, and for mass at smaller q,
+  // that kernel fills its wavefronts with several elements and wins
+  constexpr bool kGauss = std::is_same<T, double>::value && Q <= 9 && !EOUT &&
                           ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
   if constexpr (kGauss) {
     const hx_mesh_s &m = *op.mesh;
@@ -71,7 +71,8 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
-      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)((e1 - e0) * NC)), dim3(64), 0, s, a.idx, a.own, qd,
+      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)((e1 - e0) * NC)), dim3(GaussCfg<Q>::NT), 0, s,
+                         a.idx, a.own, qd,
                          tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero);
     }
     hipError_t e = hipGetLastError();

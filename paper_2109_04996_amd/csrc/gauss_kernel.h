@@ -77,19 +77,33 @@ __device__ __forceinline__ void deriv_bwd(const T *__restrict__ D0, const T (&v)
   }
 }
 
-__device__ __forceinline__ void wave_sync_g() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// One element per workgroup: one wavefront for q <= 8, two for q = 9 (81 line tiles).
+template <int Q>
+struct GaussCfg {
+  static constexpr int NT = (Q * Q <= 64) ? 64 : 128;
+};
+
+// LDS ordering between the steps of an element: within one wavefront LDS operations complete in
+// order, so the fences only stop the compiler from moving accesses; two wavefronts need a barrier.
+template <int NT>
+__device__ __forceinline__ void elem_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
 }
 
-// One element per wavefront (a workgroup is one wavefront). tab: interp [Q][P] then D [Q][Q].
+// One element per workgroup. tab: interp [Q][P] then D [Q][Q].
 template <int P, int Q, int MODE, int NC, typename T, typename TQ>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(GaussCfg<Q>::NT)
     k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
             const T *__restrict__ zero) {
-  static_assert(Q * Q <= 64 && P <= Q, "one element per wavefront, q >= p+1");
+  static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
+  constexpr int NT = GaussCfg<Q>::NT;
   static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
   constexpr int LS = Q + 1, PL = Q * LS, BUF = Q * PL;
@@ -131,7 +145,7 @@ __global__ void __launch_bounds__(64)
         for (int q = 0; q < Q; ++q) S0[AT(a, b, q)] = uq[q];
       }
     }
-    wave_sync_g();
+    elem_sync<NT>();
     // ---- along r2: thread (i = a < P, qk = b), S1[i][qj][qk]
     {
       T u[P], uq[Q];
@@ -143,7 +157,7 @@ __global__ void __launch_bounds__(64)
         for (int q = 0; q < Q; ++q) S1[AT(a, q, b)] = uq[q];
       }
     }
-    wave_sync_g();
+    elem_sync<NT>();
     // ---- along r1: thread (qj = a, qk = b) holds the line of u at (0..Q-1, a, b)
     T ul[Q];
     {
@@ -162,7 +176,7 @@ __global__ void __launch_bounds__(64)
       // transposed interpolation along r1 straight from registers: S0[i][qj][qk]
       T z[P];
       interp_bwd<P, Q, T>(tI, v, z);
-      wave_sync_g();
+      elem_sync<NT>();
       if (lane_live) {
 #pragma unroll
         for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = z[i];
@@ -174,7 +188,7 @@ __global__ void __launch_bounds__(64)
       {
         T ur[Q];
         deriv_fwd<Q, T>(tD, ul, ur);
-        wave_sync_g();
+        elem_sync<NT>();
         if (lane_live) {
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
@@ -183,7 +197,7 @@ __global__ void __launch_bounds__(64)
           }
         }
       }
-      wave_sync_g();
+      elem_sync<NT>();
       // r3 derivative on the r3 line of (qi = a, qj = b), kept in registers; r2 derivative on the
       // r2 line of (qi = a, qk = b), to S0 once every lane has read u
       T ut[Q];
@@ -198,7 +212,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
         for (int l = 0; l < Q; ++l) lj[l] = S0[AT(a, l, b)];
         deriv_fwd<Q, T>(tD, lj, us);
-        wave_sync_g();
+        elem_sync<NT>();
         if (lane_live) {
 #pragma unroll
           for (int q = 0; q < Q; ++q) S0[AT(a, q, b)] = us[q];
@@ -213,7 +227,7 @@ __global__ void __launch_bounds__(64)
       };
       load_plane(ga, 0);
       load_plane(gb, 1);
-      wave_sync_g();
+      elem_sync<NT>();
       // pointwise on r3 lines: thread (qi = a, qj = b); S1 holds ur, S0 us; vr -> S1, vs -> S0
       T vt[Q];
 #pragma unroll
@@ -230,7 +244,7 @@ __global__ void __launch_bounds__(64)
         __builtin_amdgcn_sched_barrier(0);
       }
       deriv_bwd<Q, T>(tD, vt, w);  // r3 part, on the r3 line of (a, b)
-      wave_sync_g();
+      elem_sync<NT>();
       // transposed r1 (thread (qj = a, qk = b), from S1) and r2 (thread (qi = a, qk = b), from S0)
       {
         T ri[Q], rj[Q];
@@ -246,7 +260,7 @@ __global__ void __launch_bounds__(64)
           for (int l = 0; l < Q; ++l) lj[l] = S0[AT(a, l, b)];
           deriv_bwd<Q, T>(tD, lj, rj);
         }
-        wave_sync_g();
+        elem_sync<NT>();
         if (lane_live) {
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
@@ -255,30 +269,30 @@ __global__ void __launch_bounds__(64)
           }
         }
       }
-      wave_sync_g();
+      elem_sync<NT>();
       // sum of the three parts on r3 lines, to S0 for the transposed interpolations
 #pragma unroll
       for (int k = 0; k < Q; ++k) w[k] += S0[AT(a, b, k)] + S1[AT(a, b, k)];
-      wave_sync_g();
+      elem_sync<NT>();
       if (lane_live) {
 #pragma unroll
         for (int k = 0; k < Q; ++k) S0[AT(a, b, k)] = w[k];
       }
-      wave_sync_g();
+      elem_sync<NT>();
       // transposed interpolation along r1: thread (qj = a, qk = b), S0[i][qj][qk]
       {
         T v[Q], z[P];
 #pragma unroll
         for (int q = 0; q < Q; ++q) v[q] = S0[AT(q, a, b)];
         interp_bwd<P, Q, T>(tI, v, z);
-        wave_sync_g();
+        elem_sync<NT>();
         if (lane_live) {
 #pragma unroll
           for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = z[i];
         }
       }
     }
-    wave_sync_g();
+    elem_sync<NT>();
     // ---- transposed interpolation along r2: thread (i = a < P, qk = b), S1[i][j][qk]
     {
       T v[Q], z[P];
@@ -295,7 +309,7 @@ __global__ void __launch_bounds__(64)
     T old[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
-    wave_sync_g();
+    elem_sync<NT>();
     // ---- transposed interpolation along r3 in registers: thread (i, j) -> node line (i, j, 0..P-1)
     {
       T v[Q], z[P];
