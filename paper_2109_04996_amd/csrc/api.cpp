@@ -130,8 +130,37 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
     tab.insert(tab.end(), O.begin(), O.end());
     tab.insert(tab.end(), M.begin(), M.end());
   } else {
+    // interp [Q][P], the q-point derivative [Q][Q], then the even-odd coefficients of both: the
+    // interpolation table is centro-symmetric (symmetric nodes and points), E [hq+oq][hp+op] and
+    // O [hq][hp] (hp = P/2, op = P odd, likewise q); the derivative is centro-antisymmetric,
+    // E [h][h+odd], O [h][h], M [h] (odd Q), h = Q/2, as for the collocated D above
     tab = op->b.interp;
     tab.insert(tab.end(), op->b.colloc.begin(), op->b.colloc.end());
+    const int P = op->P, Q = op->Q, hp = P / 2, opd = P & 1, hq = Q / 2, oq = Q & 1;
+    const std::vector<double> &B = op->b.interp;
+    std::vector<double> EI((hq + oq) * (hp + opd)), OI(hq * hp);
+    for (int q = 0; q < hq + oq; ++q) {
+      for (int l = 0; l < hp; ++l) EI[q * (hp + opd) + l] = 0.5 * (B[q * P + l] + B[q * P + P - 1 - l]);
+      if (opd) EI[q * (hp + opd) + hp] = B[q * P + hp];
+    }
+    for (int q = 0; q < hq; ++q)
+      for (int l = 0; l < hp; ++l) OI[q * hp + l] = 0.5 * (B[q * P + l] - B[q * P + P - 1 - l]);
+    tab.insert(tab.end(), EI.begin(), EI.end());
+    tab.insert(tab.end(), OI.begin(), OI.end());
+    const std::vector<double> &D = op->b.colloc;
+    const int h = hq, odd = oq, he = h + odd;
+    std::vector<double> E(h * he), O(h * h), M(odd * h);
+    for (int i = 0; i < h; ++i) {
+      for (int l = 0; l < h; ++l) {
+        E[i * he + l] = 0.5 * (D[i * Q + l] + D[i * Q + Q - 1 - l]);
+        O[i * h + l] = 0.5 * (D[i * Q + l] - D[i * Q + Q - 1 - l]);
+      }
+      if (odd) E[i * he + h] = D[i * Q + h];
+    }
+    for (int l = 0; l < odd * h; ++l) M[l] = D[h * Q + l];
+    tab.insert(tab.end(), E.begin(), E.end());
+    tab.insert(tab.end(), O.begin(), O.end());
+    tab.insert(tab.end(), M.begin(), M.end());
   }
   std::vector<float> tab32(tab.begin(), tab.end());
   hipError_t e;

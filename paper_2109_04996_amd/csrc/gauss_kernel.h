@@ -26,55 +26,90 @@
 
 namespace hx {
 
-// y[q] = sum_i B[q][i] u[i] (B row-major [Q][P], wave-uniform table)
+// Even-odd form of the interpolation table B [Q][P] from P symmetric nodes to Q symmetric points:
+// B[Q-1-q][P-1-i] = B[q][i] (centro-symmetric). With u_e[l] = u[l] + u[P-1-l], u_o[l] = u[l] -
+// u[P-1-l] (l < hp = P/2; u_e[hp] = u[hp] for odd P), E[q][l] = (B[q][l] + B[q][P-1-l]) / 2
+// (E[q][hp] = B[q][hp]) and O[q][l] = (B[q][l] - B[q][P-1-l]) / 2:
+//   y[q] = E_q u_e + O_q u_o,  y[Q-1-q] = E_q u_e - O_q u_o  (q < hq = Q/2),  y[hq] = E_hq u_e (odd Q).
+// The transpose uses the same E and O by columns. Half the products of the dense form.
+// Coefficient layout: E [hq + oq][hp + op], then O [hq][hp].
+template <int P, int Q>
+struct EOInterp {
+  static constexpr int hp = P / 2, op = P & 1, hq = Q / 2, oq = Q & 1;
+  static constexpr int ew = hp + op;  // row length of E
+  static constexpr int E = 0, O = (hq + oq) * ew, size = O + hq * hp;
+};
+
+// y[q] = sum_i B[q][i] u[i]
 template <int P, int Q, typename T>
-__device__ __forceinline__ void interp_fwd(const T *__restrict__ B0, const T (&u)[P], T (&y)[Q]) {
-  const const_ptr<T> B = launder_uniform(B0);
+__device__ __forceinline__ void interp_fwd(const T *__restrict__ C0, const T (&u)[P], T (&y)[Q]) {
+  const const_ptr<T> C = launder_uniform(C0);
+  using L = EOInterp<P, Q>;
+  T ue[L::ew], uo[L::hp > 0 ? L::hp : 1];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    T s = 0;
+  for (int l = 0; l < L::hp; ++l) {
+    ue[l] = u[l] + u[P - 1 - l];
+    uo[l] = u[l] - u[P - 1 - l];
+  }
+  if constexpr (L::op) ue[L::hp] = u[L::hp];
 #pragma unroll
-    for (int i = 0; i < P; ++i) s += B[q * P + i] * u[i];
-    y[q] = s;
+  for (int q = 0; q < L::hq; ++q) {
+    T d = 0, s = 0;
+#pragma unroll
+    for (int l = 0; l < L::ew; ++l) d += C[L::E + q * L::ew + l] * ue[l];
+#pragma unroll
+    for (int l = 0; l < L::hp; ++l) s += C[L::O + q * L::hp + l] * uo[l];
+    y[q] = d + s;
+    y[Q - 1 - q] = d - s;
+  }
+  if constexpr (L::oq) {
+    T d = 0;
+#pragma unroll
+    for (int l = 0; l < L::ew; ++l) d += C[L::E + L::hq * L::ew + l] * ue[l];
+    y[L::hq] = d;
   }
 }
 
 // y[i] = sum_q B[q][i] v[q]
 template <int P, int Q, typename T>
-__device__ __forceinline__ void interp_bwd(const T *__restrict__ B0, const T (&v)[Q], T (&y)[P]) {
-  const const_ptr<T> B = launder_uniform(B0);
+__device__ __forceinline__ void interp_bwd(const T *__restrict__ C0, const T (&v)[Q], T (&y)[P]) {
+  const const_ptr<T> C = launder_uniform(C0);
+  using L = EOInterp<P, Q>;
+  T ve[L::hq + L::oq], vo[L::hq > 0 ? L::hq : 1];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    T s = 0;
+  for (int m = 0; m < L::hq; ++m) {
+    ve[m] = v[m] + v[Q - 1 - m];
+    vo[m] = v[m] - v[Q - 1 - m];
+  }
+  if constexpr (L::oq) ve[L::hq] = v[L::hq];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s += B[q * P + i] * v[q];
-    y[i] = s;
+  for (int i = 0; i < L::hp; ++i) {
+    T d = 0, s = 0;
+#pragma unroll
+    for (int m = 0; m < L::hq + L::oq; ++m) d += C[L::E + m * L::ew + i] * ve[m];
+#pragma unroll
+    for (int m = 0; m < L::hq; ++m) s += C[L::O + m * L::hp + i] * vo[m];
+    y[i] = d + s;
+    y[P - 1 - i] = d - s;
+  }
+  if constexpr (L::op) {
+    T d = 0;
+#pragma unroll
+    for (int m = 0; m < L::hq + L::oq; ++m) d += C[L::E + m * L::ew + L::hp] * ve[m];
+    y[L::hp] = d;
   }
 }
 
-// y = D u and y = D^T v for the Q x Q collocated derivative on the q points (row-major [Q][Q])
+// y = D u and y = D^T v for the Q x Q derivative on the q points: even-odd form (EOLayout of
+// colloc_kernel.h; D is centro-antisymmetric on symmetric points)
 template <int Q, typename T>
-__device__ __forceinline__ void deriv_fwd(const T *__restrict__ D0, const T (&u)[Q], T (&y)[Q]) {
-  const const_ptr<T> D = launder_uniform(D0);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    T s = 0;
-#pragma unroll
-    for (int l = 0; l < Q; ++l) s += D[q * Q + l] * u[l];
-    y[q] = s;
-  }
+__device__ __forceinline__ void deriv_fwd(const T *__restrict__ C0, const T (&u)[Q], T (&y)[Q]) {
+  eo_apply<Q, T>(C0, u, y);
 }
 
 template <int Q, typename T>
-__device__ __forceinline__ void deriv_bwd(const T *__restrict__ D0, const T (&v)[Q], T (&y)[Q]) {
-  const const_ptr<T> D = launder_uniform(D0);
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    T s = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) s += D[q * Q + m] * v[q];
-    y[m] = s;
-  }
+__device__ __forceinline__ void deriv_bwd(const T *__restrict__ C0, const T (&v)[Q], T (&y)[Q]) {
+  eo_apply_t<Q, T>(C0, v, y);
 }
 
 // One element per workgroup: one wavefront for q <= 8, two for q = 9 (81 line tiles).
@@ -96,7 +131,8 @@ __device__ __forceinline__ void elem_sync() {
   }
 }
 
-// One element per workgroup. tab: interp [Q][P] then D [Q][Q].
+// One element per workgroup. tab: interp [Q][P], D [Q][Q], then the even-odd coefficients of the
+// interpolation (EOInterp) and of D (EOLayout).
 template <int P, int Q, int MODE, int NC, typename T, typename TQ>
 __global__ void __launch_bounds__(GaussCfg<Q>::NT)
     k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
@@ -122,8 +158,8 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   const int64_t eo = item / NC;
   const int c = item - (int)eo * NC;
   const int64_t e = e_begin + eo;
-  const T *const tI = tab;
-  const T *const tD = tab + Q * P;
+  const T *const tI = tab + Q * P + Q * Q;               // even-odd interpolation
+  const T *const tD = tI + EOInterp<P, Q>::size;          // even-odd derivative
   // node lanes: (i, j) = (a, b) for a, b < P; the others address node (min(a, P-1), min(b, P-1))
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
