@@ -65,6 +65,34 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // that kernel fills its wavefronts with several elements and wins
   constexpr bool kGauss = std::is_same<T, double>::value && Q <= 9 && !EOUT &&
                           ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+  if constexpr (kGauss && MODE == MODE_MASS && P == kStripP) {
+    // degree-7 mass on a mesh with strips: the strip scatter
+    const hx_mesh_s &m = *op.mesh;
+    if (m.nstrips > 0) {
+      const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
+      const dim3 block(kStrip * GaussCfg<Q>::NT);
+      for (int c = 0; c < m.nstrip_colors; ++c) {
+        const int64_t s0 = m.strip_color_start[c], s1 = m.strip_color_start[c + 1];
+        if (s1 <= s0) continue;
+        const dim3 grid((unsigned)((s1 - s0) * NC));
+        if (m.idx_affine.ptr)
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr,
+                             m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
+                             m.strip_elems.ptr, s0, zero);
+        else if (m.idx_rows.ptr)
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 1>), grid, block, 0, s, m.idx_rows.ptr,
+                             m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
+                             m.strip_elems.ptr, s0, zero);
+        else
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 0>), grid, block, 0, s, a.idx, m.strip_own.ptr,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0,
+                             zero);
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "k_gauss_strip launch");
+      return HX_OK;
+    }
+  }
   if constexpr (kGauss) {
     const hx_mesh_s &m = *op.mesh;
     const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);

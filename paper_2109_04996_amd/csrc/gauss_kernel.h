@@ -23,6 +23,7 @@
 
 #include "apply_kernel.h"
 #include "colloc_kernel.h"
+#include "hx_internal.h"
 
 namespace hx {
 
@@ -131,45 +132,25 @@ __device__ __forceinline__ void elem_sync() {
   }
 }
 
-// One element per workgroup. tab: interp [Q][P], D [Q][Q], then the even-odd coefficients of the
-// interpolation (EOInterp) and of D (EOLayout).
-template <int P, int Q, int MODE, int NC, typename T, typename TQ>
-__global__ void __launch_bounds__(GaussCfg<Q>::NT)
-    k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
-            const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
-            const T *__restrict__ zero) {
-  static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
-  constexpr int NT = GaussCfg<Q>::NT;
-  static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
-  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
-  constexpr int LS = Q + 1, PL = Q * LS, BUF = Q * PL;
-  constexpr int NCQ = (MODE == MODE_MASS) ? 1 : 6;
-  __shared__ T S0[BUF];
-  __shared__ T S1[BUF];
+// The element pipeline shared by the Gauss kernels: for one component c of element e, node lane
+// (i, j) = (a, b) ends with z[k], its element's contribution at node (i, j, k), and old[k], the
+// value its scatter adds it to (requested before the last contraction: zero where ob says the
+// lane stores first). S0, S1: this element's two LDS buffers. NT: threads per element (64 syncs
+// the wavefront, more a workgroup barrier).
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT>
+__device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict__ S1, int a, int b, bool lane_live,
+                                              int64_t e, int c, const TQ *__restrict__ qd, const T *__restrict__ tab,
+                                              const T *__restrict__ x, const int32_t (&nid)[P], uint32_t ob,
+                                              const T *__restrict__ zero, const T *__restrict__ y, T (&old)[P],
+                                              T (&z)[P]) {
+  constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+  constexpr int LS = Q + 1, PL = Q * LS;
 #define AT(i, j, k) ((k) * PL + (j) * LS + (i))
-
-  const int lt0 = threadIdx.x;
-  const bool lane_live = lt0 < Q2;
-  const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
-  const int a = lt % Q, b = lt / Q;
-  // one component of one element per block (grid = (e_end - e_begin) NC); with several
-  // components, an XCD-aware order keeps an element's components on one XCD
-  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int64_t eo = item / NC;
-  const int c = item - (int)eo * NC;
-  const int64_t e = e_begin + eo;
-  const T *const tI = tab + Q * P + Q * Q;               // even-odd interpolation
-  const T *const tD = tI + EOInterp<P, Q>::size;          // even-odd derivative
+  const T *const tI = tab + Q * P + Q * Q;       // even-odd interpolation
+  const T *const tD = tI + EOInterp<P, Q>::size;  // even-odd derivative
   // node lanes: (i, j) = (a, b) for a, b < P; the others address node (min(a, P-1), min(b, P-1))
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
-
-  int32_t nid[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
-  const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
-
-  {
     // ---- interpolate along r3 in registers: thread (i, j), S0[i][j][qk]
     {
       T u[P], uq[Q];
@@ -342,23 +323,132 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
     }
     // old values of the nodes this lane read-modify-writes (no other element of this launch
     // touches them), requested before the last contraction
-    T old[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
     elem_sync<NT>();
     // ---- transposed interpolation along r3 in registers: thread (i, j) -> node line (i, j, 0..P-1)
     {
-      T v[Q], z[P];
+      T v[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) v[q] = S1[AT(an, bn, q)];
       interp_bwd<P, Q, T>(tI, v, z);
-      if (node_lane) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
-      }
     }
-  }
 #undef AT
+}
+
+// One element per workgroup. tab: interp [Q][P], D [Q][Q], then the even-odd coefficients of the
+// interpolation (EOInterp) and of D (EOLayout).
+template <int P, int Q, int MODE, int NC, typename T, typename TQ>
+__global__ void __launch_bounds__(GaussCfg<Q>::NT)
+    k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
+            const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
+            const T *__restrict__ zero) {
+  static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
+  static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
+  constexpr int NT = GaussCfg<Q>::NT;
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
+  constexpr int BUF = Q * Q * (Q + 1);
+  __shared__ T S0[BUF];
+  __shared__ T S1[BUF];
+
+  const int lt0 = threadIdx.x;
+  const bool lane_live = lt0 < Q2;
+  const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
+  const int a = lt % Q, b = lt / Q;
+  // one component of one element per block (grid = (e_end - e_begin) NC); with several
+  // components, an XCD-aware order keeps an element's components on one XCD
+  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int64_t eo = item / NC;
+  const int c = item - (int)eo * NC;
+  const int64_t e = e_begin + eo;
+  const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
+  const bool node_lane = lane_live && a < P && b < P;
+
+  int32_t nid[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+  const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
+
+  T old[P], z[P];
+  gauss_element<P, Q, MODE, NC, T, TQ, NT>(S0, S1, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y, old, z);
+  if (node_lane) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
+  }
+}
+
+// The Gauss kernel with the strip scatter of k_colloc_strip (degree 7 meshes with strips): a
+// workgroup takes a strip of up to kStrip elements, one or two wavefronts per element, runs the
+// element pipeline on each, and sums the shared r1 faces in LDS -- element w+1 leaves its r1 = -1
+// face there, element w adds it to its own r1 = +1 face and writes it once. Other nodes follow the
+// strip ownership (store by the first writer in strip order, read-modify-write by later ones).
+// IDX: node ids as in k_colloc_strip (0 per node, 1 per r1-row, 2 affine per element).
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX>
+__global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
+    k_gauss_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
+                  const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
+                  const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
+  static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
+  constexpr int NTE = GaussCfg<Q>::NT;  // threads per element
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
+  constexpr int BUF = Q * Q * (Q + 1);
+  __shared__ T s0[kStrip][BUF];
+  __shared__ T s1[kStrip][BUF];
+  __shared__ T face[kStrip][P2];  // element w's r1 = -1 face, [k][j]
+
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid / NTE);  // element slot (uniform in a wavefront)
+  const int lt0 = tid - w * NTE;
+  const bool lane_live = lt0 < Q2;
+  const int lt = lane_live ? lt0 : Q2 - 1;
+  const int a = lt % Q, b = lt / Q;
+  // one component of one strip per block; several components: XCD-aware order
+  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int sl = item / NC, c = item - sl * NC;
+  const int32_t *const se = selems + (s_begin + sl) * kStrip;
+  const int32_t el = se[w];
+  const bool live = el >= 0;
+  const int64_t ee = live ? el : se[0];  // a slot past the strip's end works on a valid element
+  const bool has_prev = live && w > 0;
+  const bool has_next = (w + 1 < kStrip) && se[w < kStrip - 1 ? w + 1 : w] >= 0 && live;
+  const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
+  const bool node_lane = lane_live && a < P && b < P;
+  const bool skip = has_prev && node_lane && a == 0;  // written by the previous element
+
+  int32_t nid[P];
+  if constexpr (IDX == 2) {
+    const int32_t *af = idx + ee * 4;
+    const int32_t base = af[0] + an, sj = af[1], sk = af[2];
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = base + bn * sj + k * sk;
+  } else if constexpr (IDX == 1) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P2 + k * P + bn) + an;
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + ee * P3 + k * P2 + bn * P + an);
+  }
+  const uint32_t ob = (live && node_lane && !skip) ? (uint32_t)sown[ee * P2 + b * P + a] : 0xffffu;
+
+  T old[P], z[P];
+  gauss_element<P, Q, MODE, NC, T, TQ, NTE>(s0[w], s1[w], a, b, lane_live, ee, c, qd, tab, x, nid, ob, zero, y, old,
+                                            z);
+  T out[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) out[k] = old[k] + z[k];
+  if (skip) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) face[w][k * P + b] = out[k];
+  }
+  __syncthreads();
+  if (has_next && node_lane && a == P - 1) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) out[k] += face[w + 1][k * P + b];
+  }
+  if (live && node_lane && !skip) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = out[k];
+  }
 }
 
 }  // namespace hx

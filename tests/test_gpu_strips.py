@@ -1,6 +1,6 @@
-"""GPU tests of the strip scatter of the degree-7 collocated apply.
+"""GPU tests of the strip scatter of the degree-7 applies (collocated diffusion, Gauss-point mass).
 
-The strip kernel scatters chains of face-adjacent elements together. Its results are checked
+The strip kernels scatter chains of face-adjacent elements together. Their results are checked
 against the FP64 oracle on meshes whose elements have random proper rotations (so chains break
 and strips of every length from 1 to 8 occur), and at the full benchmark size against the
 E-vector path (element kernel, no scatter) summed node by node.
@@ -67,13 +67,14 @@ def test_strips_are_built_for_degree_7_only():
         assert pr.stats["nstrips"] == 0
 
 
-@pytest.mark.parametrize("ncomp", [1, 3])  # three components run the per-element kernel on the same mesh
-def test_strip_apply_rotated_elements_matches_oracle(ncomp):
+@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, q):
     p, N = 7, 4
-    print(f"\n[case] strips rotated N={N} p={p} ncomp={ncomp}", flush=True)
+    print(f"\n[case] strips rotated N={N} p={p} q={q} {kind} ncomp={ncomp}", flush=True)
     mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=5), p, 0.15, seed=ncomp)
-    A = fem.assemble(mesh, p, p + 1, "gll", "diffusion")
-    with Problem(N, p, p + 1, "gll", "diffusion", ncomp=ncomp, mesh=mesh) as pr:
+    A = fem.assemble(mesh, p, q, rule, kind)
+    with Problem(N, p, q, rule, kind, ncomp=ncomp, mesh=mesh) as pr:
         assert 0 < pr.stats["nstrips"] < mesh["nelem"]
         x = uniform_vector(mesh["nnodes"], 7, ncomp)
         y = pr.apply(pr.to_dev(x)).cpu().numpy()
@@ -98,15 +99,16 @@ def _scatter_evector(pr, ye):
     return y
 
 
+@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
 @pytest.mark.parametrize("N,frac", [(9, 0.0), (9, 0.2), (48, 0.0)])
-def test_strip_apply_matches_evector_sum(N, frac):
+def test_strip_apply_matches_evector_sum(N, frac, kind, rule, q):
     # N = 9: chains of 9 cut into 8 + 1; N = 48: the benchmark mesh (6 strips of 8 per chain)
     p = 7
-    print(f"\n[case] strips vs E-vector N={N} frac={frac}", flush=True)
+    print(f"\n[case] strips vs E-vector N={N} frac={frac} {kind} q={q}", flush=True)
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
     if frac > 0:
         mesh = rotate_elements(mesh, p, frac, seed=11)
-    with Problem(N, p, p + 1, "gll", "diffusion", mesh=mesh) as pr:
+    with Problem(N, p, q, rule, kind, mesh=mesh) as pr:
         assert pr.stats["nstrips"] > 0
         x = pr.to_dev(uniform_vector(mesh["nnodes"], 1))
         y = pr.apply(x)
