@@ -196,6 +196,14 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
                                                      flexible=1)
     _, out["ir_fp32op_cheb4_bf16mfma"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
                                                       cheb_prec=hx.HX_BF16, inner_qdata=hx.HX_FP32, flexible=1)
+    # the same matrix cores with hi + lo bfloat16 operands
+    _, out["fp64_fcg_cheb4_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV,
+                                                      cheb_prec=hx.HX_BF16_SPLIT, flexible=1)
+    _, out["fp64_cg_cheb4_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV,
+                                                     cheb_prec=hx.HX_BF16_SPLIT, flexible=0)
+    _, out["ir_fp32op_cheb4_bf16split"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
+                                                       cheb_prec=hx.HX_BF16_SPLIT, inner_qdata=hx.HX_FP32,
+                                                       flexible=1)
     pr.close()
     return out
 

@@ -61,7 +61,11 @@ enum {
 
 enum { HX_GAUSS = 0, HX_GLL = 1 };          /* quadrature rule families               */
 enum { HX_MASS = 0, HX_DIFFUSION = 1 };      /* B and A of the bake-off problems       */
-enum { HX_FP64 = 0, HX_FP32 = 1, HX_BF16 = 2 };
+/* Arithmetic precisions. HX_BF16: matrix-core products of operands rounded to
+ * bfloat16, accumulated in FP32. HX_BF16_SPLIT: the same matrix cores with every
+ * operand carried as hi + lo, both bfloat16 (lo the rounding error of hi), and the
+ * products hi*hi + hi*lo + lo*hi accumulated in FP32 (about 16 significant bits). */
+enum { HX_FP64 = 0, HX_FP32 = 1, HX_BF16 = 2, HX_BF16_SPLIT = 3 };
 
 typedef struct hx_mesh_s *hx_mesh;
 typedef struct hx_basis_s *hx_basis;
@@ -192,11 +196,13 @@ hx_status hx_op_apply(hx_op op, const double *x, double *y, hx_stream s);
  * FP32. x, y: device floats. Asynchronous. Errors: HX_EINVAL, HX_ENOMEM, HX_EHIP. */
 hx_status hx_op_apply_f32(hx_op op, int qdata_prec, const float *x, float *y, hx_stream s);
 
-/* y = A x with the basis contractions on bf16 matrix cores (operands rounded
- * to bfloat16, FP32 accumulation), the pointwise operator in FP32. x, y:
- * device floats. For HX_DIFFUSION, ncomp = 1. Asynchronous.
- * Errors: HX_EINVAL, HX_EUNSUPPORTED, HX_ENOMEM, HX_EHIP. */
-hx_status hx_op_apply_bf16(hx_op op, const float *x, float *y, hx_stream s);
+/* y = A x with the basis contractions on bf16 matrix cores, the pointwise
+ * operator in FP32 on a bfloat16 copy of the geometric factors (made at the
+ * first call). prec: HX_BF16 or HX_BF16_SPLIT (operand representation, see the
+ * precision constants). x, y: device floats. HX_DIFFUSION, ncomp = 1, p + 1 <= 8
+ * and q <= 8 only. Asynchronous.
+ * Errors: HX_EINVAL (null pointer, bad prec), HX_EUNSUPPORTED, HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_apply_bf16(hx_op op, int prec, const float *x, float *y, hx_stream s);
 
 /* E-vector action (the bake-off kernel: the element-local part only):
  * y_e[(e*ncomp + c)*(p+1)^3 + l] = (A_e x_e)_l for caller element e, FP64.
@@ -237,7 +243,7 @@ typedef struct {
   int cheb_degree;     /* Chebyshev steps per application (>= 1)             */
   double cheb_ratio;   /* lam_lo = lam_hi / cheb_ratio                        */
   int cheb_prec;       /* operator precision in the Chebyshev polynomial:
-                          HX_FP64, HX_FP32 or HX_BF16                          */
+                          HX_FP64, HX_FP32, HX_BF16 or HX_BF16_SPLIT          */
   int lanczos_steps;   /* steps of the lam_max estimate (>= 2)               */
   double inner_rtol;   /* IR: inner FP32 solve tolerance (relative to the outer
                           residual; loosened to 0.5 rtol ||b|| / ||r|| when that
@@ -247,8 +253,8 @@ typedef struct {
                           one inner solve needs)                               */
   int inner_qdata;     /* IR: HX_FP64 or HX_FP32 geometric factors            */
   int flexible;        /* 1: flexible CG (Polak-Ribiere beta) for preconditioners
-                          that are not exactly linear or symmetric (HX_BF16
-                          Chebyshev); 0: plain PCG                               */
+                          that are not exactly linear or symmetric (the bf16
+                          Chebyshev forms); 0: plain PCG                         */
   hx_mlp mlp;          /* HX_PC_MLP: the trained network (flexible CG is used)  */
   int fallback;        /* HX_PC_MLP: HX_PC_JACOBI or HX_PC_CHEBYSHEV, run from the
                           current iterate when the learned solve breaks down or

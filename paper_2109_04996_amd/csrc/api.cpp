@@ -209,10 +209,11 @@ extern "C" hx_status hx_op_apply_f32(hx_op op, int qdata_prec, const float *x, f
   return launch_apply(*op, qdata_prec == HX_FP32 ? Prec::F32_Q32 : Prec::F32_Q64, false, a, st);
 }
 
-extern "C" hx_status hx_op_apply_bf16(hx_op op, const float *x, float *y, hx_stream s) {
+extern "C" hx_status hx_op_apply_bf16(hx_op op, int prec, const float *x, float *y, hx_stream s) {
   if (!op || !x || !y) return fail(HX_EINVAL, "null argument");
+  if (prec != HX_BF16 && prec != HX_BF16_SPLIT) return fail(HX_EINVAL, "prec must be HX_BF16 or HX_BF16_SPLIT");
   if (op->kind != HX_DIFFUSION || op->ncomp != 1) return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
-  return launch_apply_bf16(*op, x, y, static_cast<hipStream_t>(s));
+  return launch_apply_bf16(*op, prec == HX_BF16_SPLIT, x, y, static_cast<hipStream_t>(s));
 }
 
 extern "C" hx_status hx_op_apply_elem(hx_op op, const double *x, double *y_e, hx_stream s) {

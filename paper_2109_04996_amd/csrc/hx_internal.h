@@ -157,6 +157,6 @@ enum class Prec { F64, F32_Q64, F32_Q32 };
 hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyArgs &a, hipStream_t s);
 hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s, int *bad_det);
 hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
-hx_status launch_apply_bf16(hx_op_s &op, const float *x, float *y, hipStream_t s);
+hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s);
 
 }  // namespace hx

@@ -4,13 +4,16 @@
 // (Benchmarks section: tensor-product sum factorization) done as a small matrix product on
 // V_MFMA_F32_16X16X16_BF16: operands rounded to bfloat16, products accumulated in FP32.
 //
-// Work decomposition: one element per wavefront. A contraction of dimension d of a 3-D
-// array X (held in LDS as FP32) with a 1D table T (m_out x n_d) is the product
-// T (m_out x n_d) * X_d (n_d x columns), the columns being the pairs of the two other
-// indices (at most 64 for q <= 8), taken 16 at a time: one MFMA per 16 columns, with T
-// and the column block zero-padded to 16 x 16. Lane l supplies T[l%16][4(l/16)..+3] (A
-// operand) and X[4(l/16)..+3][column l%16] (B operand), and receives
-// Y[4(l/16)..+3][column l%16] (accumulator).
+// Work decomposition: one element per wavefront, four per workgroup, each wavefront with its
+// own LDS buffers (so the steps synchronise the wavefront only). Every element is padded to
+// 8 x 8 x 8 (nodes and points beyond P or Q are zero; the tables are zero-padded to 8 x 8),
+// so one kernel serves every P, Q <= 8. A contraction of dimension d with a table T (8 x 8)
+// is T * X_d, X_d the 8 x 64 matrix whose columns are the pairs of the two other indices.
+// Two 16-column groups share one MFMA: the A operand is diag(T, T) and the B operand stacks
+// the first group's 8 rows over the second's, so the 16 x 16 x 16 product has no zero
+// padding and a contraction is two MFMAs. Lane l supplies A[l%16][4(l/16)..+3] and
+// B[4(l/16)..+3][l%16] and receives D[4(l/16)..+3][l%16]: its 4 inputs and 4 outputs are the
+// same column, entries kb..kb+3 (kb = 0 or 4) along d, of group (l/32) of the pair.
 //
 // The pointwise operator runs in FP32 on a bfloat16 copy of the stored FP64 qdata. The
 // scatter is the atomic-free colored scatter of the FP64 kernels.
@@ -24,162 +27,224 @@ namespace {
 __device__ __forceinline__ short to_bf16(float f) { return (short)f32_to_bf16_bits(f); }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return bf16_bits_to_f32(h); }
 
-// A operand of a table T (rows x cols, row-major, FP32 in LDS), optionally transposed:
-// lane l holds T[l%16][4(l/16)+t] (or T^T), zero outside the table.
-__device__ __forceinline__ bf16x4 table_operand(const float *T, int rows, int cols, bool transpose) {
-  const int l = threadIdx.x & 63, m = l & 15, kb = 4 * (l >> 4);
-  bf16x4 a;
+constexpr int kBfMaxQ = 8;
+constexpr int kBfWpb = 4;                 // elements (wavefronts) per workgroup
+constexpr int kSJ = 10, kSK = 80;         // LDS strides of j and k (i unit stride), padded against bank conflicts
+constexpr int kBuf = kSK * 8;             // floats per 8 x 8 x 8 buffer
+constexpr int kQdBf16 = 6 * 512;          // bf16 qdata values per element (padded to 8 x 8 x 8 points)
+
+__device__ __forceinline__ int at8(int i, int j, int k) { return i + kSJ * j + kSK * k; }
+
+// An operand carried as hi + lo, both bfloat16 (lo = the rounding error of hi): products of
+// such pairs, hi*hi + hi*lo + lo*hi accumulated in FP32, carry about 16 significant bits.
+struct Opnd {
+  bf16x4 hi, lo;
+};
+
+__device__ __forceinline__ short bf16_hi(float v) { return (short)f32_to_bf16_bits(v); }
+__device__ __forceinline__ short bf16_lo(float v, short hi) { return to_bf16(v - bf16_bits_to_f32((uint16_t)hi)); }
+
+// A operand diag(T, T) of a table T (rows x cols, row-major FP32, zero-padded to 8 x 8), or of
+// its transpose: lane l holds A[l%16][4(l/16)+t].
+__device__ __forceinline__ Opnd diag_operand(const float *__restrict__ T, int rows, int cols, bool transpose,
+                                             int l) {
+  const int m = l & 15, kb = 4 * (l >> 4);
+  Opnd a;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int k = kb + t;
+    const int kk = kb + t;
     float v = 0.f;
-    if (!transpose) {
-      if (m < rows && k < cols) v = T[m * cols + k];
-    } else {
-      // (T^T)[m][k] = T[k][m]; T^T has cols rows and rows cols
-      if (m < cols && k < rows) v = T[k * cols + m];
+    if ((m >> 3) == (kk >> 3)) {
+      const int r = m & 7, c = kk & 7;
+      if (!transpose) {
+        if (r < rows && c < cols) v = T[r * cols + c];
+      } else if (c < rows && r < cols) {
+        v = T[c * cols + r];  // (T^T)[r][c] = T[c][r]
+      }
     }
-    a[t] = to_bf16(v);
+    const short h = bf16_hi(v);
+    a.hi[t] = h;
+    a.lo[t] = bf16_lo(v, h);
   }
   return a;
 }
 
-// Y = A x_d X: contract dimension DIM (0 fastest) of X (sizes n0, n1, n2 along dims 0, 1, 2, strides
-// 1, n0, n0*n1) with the operand A (m_out rows, n_d columns); Y has dimension DIM replaced by m_out
-// and the same stride convention. ACC: add into Y instead of overwriting.
-template <int DIM, bool ACC>
-__device__ __forceinline__ void contract(const float *X, int n0, int n1, int n2, float *Y, int m_out, bf16x4 A) {
-  const int l = threadIdx.x & 63, col = l & 15, kb = 4 * (l >> 4);
-  const int nd = DIM == 0 ? n0 : DIM == 1 ? n1 : n2;
-  // the two other dimensions, in increasing order: (u, v) with sizes (nu, nv)
-  const int nu = DIM == 0 ? n1 : n0, nv = DIM == 2 ? n1 : n2;
-  // input strides
-  const int sx0 = 1, sx1 = n0, sx2 = n0 * n1;
-  const int sxd = DIM == 0 ? sx0 : DIM == 1 ? sx1 : sx2;
-  const int sxu = DIM == 0 ? sx1 : sx0, sxv = DIM == 2 ? sx1 : sx2;
-  // output sizes and strides (dimension DIM has m_out entries)
-  const int y0 = DIM == 0 ? m_out : n0, y1 = DIM == 1 ? m_out : n1;
-  const int sy1 = y0, sy2 = y0 * y1;
-  const int syd = DIM == 0 ? 1 : DIM == 1 ? sy1 : sy2;
-  const int syu = DIM == 0 ? sy1 : 1, syv = DIM == 2 ? sy1 : sy2;
-  const int ncols = nu * nv;
-  for (int c0 = 0; c0 < ncols; c0 += 16) {
-    const int c = c0 + col;
-    const bool cv = c < ncols;
-    const int u = cv ? c % nu : 0, v = cv ? c / nu : 0;
-    bf16x4 b;
+// Y = T x_DIM X on 8 x 8 x 8 buffers (A = diag(T, T)); ACC adds into Y. X and Y may not be the
+// same buffer unless every lane's column is its own (it is: a lane reads and writes one column).
+template <int DIM, bool ACC, bool SPLIT>
+__device__ __forceinline__ void contract8(const float *X, float *Y, const Opnd &A, int l) {
+  constexpr int sd = DIM == 0 ? 1 : DIM == 1 ? kSJ : kSK;  // stride of the contracted index
+  constexpr int su = DIM == 0 ? kSJ : 1;                   // the two other indices (u, v), u first
+  constexpr int sv = DIM == 2 ? kSJ : kSK;
+  const int col = l & 15, kq = l >> 4, grp = kq >> 1, kb = 4 * (kq & 1);
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const int c = (2 * pair + grp) * 16 + col;  // column 0..63 = u + 8 v
+    const int base = (c & 7) * su + (c >> 3) * sv + kb * sd;
+    bf16x4 b, blo;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int k = kb + t;
-      b[t] = to_bf16((cv && k < nd) ? X[k * sxd + u * sxu + v * sxv] : 0.f);
+      const float v = X[base + t * sd];
+      const short h = bf16_hi(v);
+      b[t] = h;
+      if (SPLIT) blo[t] = bf16_lo(v, h);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b, acc, 0, 0, 0);
-    if (cv) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.hi, b, acc, 0, 0, 0);
+    if (SPLIT) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.hi, blo, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.lo, b, acc, 0, 0, 0);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = kb + t;
-        if (r < m_out) {
-          float *dst = Y + r * syd + u * syu + v * syv;
-          if (ACC)
-            *dst += acc[t];
-          else
-            *dst = acc[t];
-        }
-      }
+    for (int t = 0; t < 4; ++t) {
+      if (ACC)
+        Y[base + t * sd] += acc[t];
+      else
+        Y[base + t * sd] = acc[t];
     }
   }
 }
 
-constexpr int kBfMaxQ = 8;
-constexpr int kBfBuf = kBfMaxQ * kBfMaxQ * kBfMaxQ;
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__global__ void __launch_bounds__(64)
+// idx: one node id per element node, or (AFF) {base, s_j, s_k} per element (node (i, j, k) =
+// base + i + j s_j + k s_k). Every global load the element needs -- its x, the old y of the
+// nodes it read-modify-writes (no other element of this launch touches them) and its qdata --
+// is issued before the first contraction, so their latencies overlap the matrix-core chain.
+template <bool AFF, bool SPLIT>
+__global__ void __launch_bounds__(kBfWpb * 64)
     k_diff_bf16(int P, int Q, const int32_t *__restrict__ idx, const uint16_t *__restrict__ own,
                 const uint16_t *__restrict__ qd16, const float *__restrict__ tab, const float *__restrict__ x,
-                float *__restrict__ y, int64_t e_begin) {
-  __shared__ float X0[kBfBuf], X1[kBfBuf], X2[kBfBuf], X3[kBfBuf];
-  __shared__ float sI[kBfMaxQ * kBfMaxQ], sD[kBfMaxQ * kBfMaxQ];
-  const int l = threadIdx.x;
-  const int64_t e = e_begin + blockIdx.x;
-  const int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
-  for (int t = l; t < Q * P; t += 64) sI[t] = tab[t];
-  for (int t = l; t < Q * Q; t += 64) sD[t] = tab[Q * P + t];
-  // gather u into X0 [k][j][i]
-  for (int t = l; t < P3; t += 64) X0[t] = x[idx[e * P3 + t]];
-  __syncthreads();
-  const bf16x4 aI = table_operand(sI, Q, P, false);   // interp: Q x P
-  const bf16x4 aIt = table_operand(sI, Q, P, true);   // transposed interp: P x Q
-  const bf16x4 aD = table_operand(sD, Q, Q, false);   // derivative on the q points: Q x Q
-  const bf16x4 aDt = table_operand(sD, Q, Q, true);   // its transpose
-  // interpolate to the q^3 points
-  contract<0, false>(X0, P, P, P, X1, Q, aI);  // X1: (Q, P, P)
-  __syncthreads();
-  contract<1, false>(X1, Q, P, P, X2, Q, aI);  // X2: (Q, Q, P)
-  __syncthreads();
-  contract<2, false>(X2, Q, Q, P, X3, Q, aI);  // X3: (Q, Q, Q) = u at the points
-  __syncthreads();
-  // reference gradient at the points
-  contract<0, false>(X3, Q, Q, Q, X0, Q, aD);
-  contract<1, false>(X3, Q, Q, Q, X1, Q, aD);
-  contract<2, false>(X3, Q, Q, Q, X2, Q, aD);
-  __syncthreads();
-  // pointwise: (vr, vs, vt) = G (ur, us, ut), qdata layout [e][qc][m][qb][qa]
-  const uint16_t *qe = qd16 + e * (int64_t)(6 * Q3);
-  for (int pt = l; pt < Q3; pt += 64) {
-    const int qc = pt / Q2, ab = pt - qc * Q2;
-    const uint16_t *g = qe + qc * 6 * Q2 + ab;
-    const float g0 = from_bf16(g[0]), g1 = from_bf16(g[Q2]), g2 = from_bf16(g[2 * Q2]);
-    const float g3 = from_bf16(g[3 * Q2]), g4 = from_bf16(g[4 * Q2]), g5 = from_bf16(g[5 * Q2]);
-    const float ur = X0[pt], us = X1[pt], ut = X2[pt];
-    X0[pt] = g0 * ur + g1 * us + g2 * ut;
-    X1[pt] = g1 * ur + g3 * us + g4 * ut;
-    X2[pt] = g2 * ur + g4 * us + g5 * ut;
+                float *__restrict__ y, int64_t e_begin, int64_t e_end, const float *__restrict__ zero) {
+  __shared__ float sbuf[kBfWpb][3][kBuf];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int64_t e = e_begin + (int64_t)blockIdx.x * kBfWpb + w;
+  const bool live = e < e_end;
+  const int64_t ee = live ? e : e_begin;
+  float *const U = sbuf[w][0];
+  float *const G0 = sbuf[w][1];
+  float *const G1 = sbuf[w][2];
+  const int P2 = P * P, P3 = P2 * P;
+  // node lane (i, j) walks its column k; point lane (a, b) walks its column c
+  const int gi = l & 7, gj = l >> 3;
+  const bool node_lane = live && gi < P && gj < P;
+  int32_t nid[8];
+  if constexpr (AFF) {
+    const int32_t *af = idx + ee * 4;
+    const int32_t base = af[0] + gi + gj * af[1], sk = af[2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nid[k] = base + k * sk;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nid[k] = (node_lane && k < P) ? idx[ee * P3 + gi + P * gj + P2 * k] : 0;
   }
-  __syncthreads();
-  // transposed gradient, summed into X3
-  contract<0, false>(X0, Q, Q, Q, X3, Q, aDt);
-  __syncthreads();
-  contract<1, true>(X1, Q, Q, Q, X3, Q, aDt);
-  __syncthreads();
-  contract<2, true>(X2, Q, Q, Q, X3, Q, aDt);
-  __syncthreads();
-  // transposed interpolation back to the nodes
-  contract<2, false>(X3, Q, Q, Q, X0, P, aIt);  // (Q, Q, P)
-  __syncthreads();
-  contract<1, false>(X0, Q, Q, P, X1, P, aIt);  // (Q, P, P)
-  __syncthreads();
-  contract<0, false>(X1, Q, P, P, X2, P, aIt);  // (P, P, P)
-  __syncthreads();
-  // colored scatter: thread (i, j) walks the column k
-  if (l < P2) {
-    const uint32_t ob = own[e * P2 + l];
-    for (int k = 0; k < P; ++k) {
-      const int t = l + k * P2;
-      float *dst = y + idx[e * P3 + t];
-      const float v = X2[t];
-      if (ob & (1u << k))
-        *dst = v;
-      else
-        *dst += v;
+  const uint32_t ob = node_lane ? (uint32_t)own[ee * P2 + gj * P + gi] : 0xffffu;
+  float u[8], old[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const bool in = node_lane && k < P;
+    const float xv = x[in ? nid[k] : 0];  // lanes off the element read a valid address and drop it
+    u[k] = in ? xv : 0.f;
+    old[k] = *((in && !(ob & (1u << k))) ? y + nid[k] : zero);
+  }
+  // qdata of this lane's point row (qa = 0..7 at qb = l % 8, qc = l / 8): six 16-byte loads from
+  // the padded bf16 copy [e][qc][m][qb][qa] (8 x 6 x 8 x 8 per element, zero past Q)
+  const int pb = l & 7, pc = l >> 3;
+  uint4 g[6];
+  {
+    const uint4 *qv = reinterpret_cast<const uint4 *>(qd16 + ee * (int64_t)kQdBf16 + (pc * 6) * 64 + pb * 8);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) g[m] = qv[m * 8];  // planes (pc, m) are 64 values = 8 uint4 apart
+  }
+
+  const float *tI = tab, *tD = tab + Q * P;                 // interp [Q][P], q-point derivative [Q][Q]
+  const Opnd aI = diag_operand(tI, Q, P, false, l);   // nodes -> points
+  const Opnd aIt = diag_operand(tI, Q, P, true, l);   // points -> nodes
+  const Opnd aD = diag_operand(tD, Q, Q, false, l);
+  const Opnd aDt = diag_operand(tD, Q, Q, true, l);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) U[at8(gi, gj, k)] = u[k];
+  wave_lds_sync();
+  // interpolate to the points: (a, j, k) -> (a, b, k) -> (a, b, c)
+  contract8<0, false, SPLIT>(U, G0, aI, l);
+  wave_lds_sync();
+  contract8<1, false, SPLIT>(G0, G1, aI, l);
+  wave_lds_sync();
+  contract8<2, false, SPLIT>(G1, U, aI, l);
+  wave_lds_sync();
+  // reference gradient at the points: ur -> G0, us -> G1, ut -> U (in place: a lane reads and
+  // writes only its own column)
+  contract8<0, false, SPLIT>(U, G0, aD, l);
+  contract8<1, false, SPLIT>(U, G1, aD, l);
+  wave_lds_sync();
+  contract8<2, false, SPLIT>(U, U, aD, l);
+  wave_lds_sync();
+  // pointwise: (vr, vs, vt) = G (ur, us, ut) on the lane's point row; padded points have G = 0
+#pragma unroll
+  for (int qa = 0; qa < 8; ++qa) {
+    const int pt = at8(qa, pb, pc);
+    float gm[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      const uint32_t word = qa < 2 ? g[m].x : qa < 4 ? g[m].y : qa < 6 ? g[m].z : g[m].w;
+      gm[m] = (qa & 1) ? __builtin_bit_cast(float, word & 0xffff0000u) : __builtin_bit_cast(float, word << 16);
     }
+    const float g0 = gm[0], g1 = gm[1], g2 = gm[2], g3 = gm[3], g4 = gm[4], g5 = gm[5];
+    const float ur = G0[pt], us = G1[pt], ut = U[pt];
+    G0[pt] = g0 * ur + g1 * us + g2 * ut;
+    G1[pt] = g1 * ur + g3 * us + g4 * ut;
+    U[pt] = g2 * ur + g4 * us + g5 * ut;
+  }
+  wave_lds_sync();
+  // transposed gradient, summed into U
+  contract8<2, false, SPLIT>(U, U, aDt, l);
+  wave_lds_sync();
+  contract8<0, true, SPLIT>(G0, U, aDt, l);
+  wave_lds_sync();
+  contract8<1, true, SPLIT>(G1, U, aDt, l);
+  wave_lds_sync();
+  // transposed interpolation back to the nodes: (a, b, c) -> (a, b, k) -> (a, j, k) -> (i, j, k)
+  contract8<2, false, SPLIT>(U, G0, aIt, l);
+  wave_lds_sync();
+  contract8<1, false, SPLIT>(G0, G1, aIt, l);
+  wave_lds_sync();
+  contract8<0, false, SPLIT>(G1, U, aIt, l);
+  wave_lds_sync();
+  // colored scatter: owners store, the others add to the old value loaded above
+  if (node_lane) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < P) y[nid[k]] = old[k] + U[at8(gi, gj, k)];
   }
 }
 
-__global__ void k_qdata_bf16(int64_t n, const double *__restrict__ a, uint16_t *__restrict__ b) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    b[t] = f32_to_bf16_bits((float)a[t]);
+// FP64 qdata [e][qc][m][qb][qa] (Q^3 points) -> bfloat16 [e][qc][m][qb][qa] padded to 8 x 8 x 8
+// points, zero past Q (round to nearest even)
+__global__ void k_qdata_bf16(int64_t nout, int Q, const double *__restrict__ a, uint16_t *__restrict__ b) {
+  const int Q2 = Q * Q, Q3 = Q2 * Q;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nout; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / kQdBf16;
+    const int r = (int)(t - e * kQdBf16);
+    const int qc = r / 384, m = (r / 64) % 6, qb = (r / 8) % 8, qa = r % 8;
+    float v = 0.f;
+    if (qa < Q && qb < Q && qc < Q) v = (float)a[e * 6 * Q3 + (qc * 6 + m) * Q2 + qb * Q + qa];
+    b[t] = f32_to_bf16_bits(v);
+  }
 }
 
 }  // namespace
 
-hx_status launch_apply_bf16(hx_op_s &op, const float *x, float *y, hipStream_t s) {
+hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s) {
   if (op.kind != HX_DIFFUSION || op.ncomp != 1) return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
   if (op.P > kBfMaxQ || op.Q > kBfMaxQ) return fail(HX_EUNSUPPORTED, "the bf16 operator supports p+1 <= 8 and q <= 8");
   if (!op.qdata_bf16.ptr) {
-    HX_HIP(op.qdata_bf16.alloc(op.qdata.count));
-    hipLaunchKernelGGL(k_qdata_bf16, dim3(1024), dim3(256), 0, s, (int64_t)op.qdata.count, op.qdata.ptr,
-                       op.qdata_bf16.ptr);
+    const int64_t nout = op.mesh->nelem * (int64_t)kQdBf16;
+    HX_HIP(op.qdata_bf16.alloc((size_t)nout));
+    hipLaunchKernelGGL(k_qdata_bf16, dim3(1024), dim3(256), 0, s, nout, op.Q, op.qdata.ptr, op.qdata_bf16.ptr);
     // tables: interp [Q][P] then the q-point derivative [Q][Q] (for the collocated rule: identity, D)
     std::vector<float> t;
     if (op.colloc) {
@@ -194,11 +259,26 @@ hx_status launch_apply_bf16(hx_op_s &op, const float *x, float *y, hipStream_t s
   }
   const hx_mesh_s &m = *op.mesh;
   if (m.nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(float) * m.nnodes, s));
+  const float *zero = reinterpret_cast<const float *>(m.zeros.ptr);
   for (int c = 0; c < m.ncolors; ++c) {
     const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
     if (e1 <= e0) continue;
-    hipLaunchKernelGGL(k_diff_bf16, dim3((unsigned)(e1 - e0)), dim3(64), 0, s, op.P, op.Q, m.idx.ptr, m.own.ptr,
-                       op.qdata_bf16.ptr, op.tab_bf16.ptr, x, y, e0);
+    const dim3 grid((unsigned)((e1 - e0 + kBfWpb - 1) / kBfWpb)), block(kBfWpb * 64);
+    if (m.idx_affine.ptr) {
+      if (split)
+        hipLaunchKernelGGL((k_diff_bf16<true, true>), grid, block, 0, s, op.P, op.Q, m.idx_affine.ptr, m.own.ptr,
+                           op.qdata_bf16.ptr, op.tab_bf16.ptr, x, y, e0, e1, zero);
+      else
+        hipLaunchKernelGGL((k_diff_bf16<true, false>), grid, block, 0, s, op.P, op.Q, m.idx_affine.ptr, m.own.ptr,
+                           op.qdata_bf16.ptr, op.tab_bf16.ptr, x, y, e0, e1, zero);
+    } else {
+      if (split)
+        hipLaunchKernelGGL((k_diff_bf16<false, true>), grid, block, 0, s, op.P, op.Q, m.idx.ptr, m.own.ptr,
+                           op.qdata_bf16.ptr, op.tab_bf16.ptr, x, y, e0, e1, zero);
+      else
+        hipLaunchKernelGGL((k_diff_bf16<false, false>), grid, block, 0, s, op.P, op.Q, m.idx.ptr, m.own.ptr,
+                           op.qdata_bf16.ptr, op.tab_bf16.ptr, x, y, e0, e1, zero);
+    }
   }
   HX_HIP(hipGetLastError());
   return HX_OK;

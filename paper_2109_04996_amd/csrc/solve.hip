@@ -364,10 +364,10 @@ hx_status apply_T(Ctx &c, const double *x, double *y, int) {
   return launch_apply(c.op, Prec::F64, false, a, c.s);
 }
 
-// prec: HX_FP64 (FP64 qdata), HX_FP32 (FP32 qdata), HX_BF16 (matrix-core operator)
+// prec: HX_FP64 (FP64 qdata), HX_FP32 (FP32 qdata), HX_BF16 / HX_BF16_SPLIT (matrix-core operator)
 hx_status apply_T(Ctx &c, const float *x, float *y, int prec) {
   ++c.applies;
-  if (prec == HX_BF16) return launch_apply_bf16(c.op, x, y, c.s);
+  if (prec == HX_BF16 || prec == HX_BF16_SPLIT) return launch_apply_bf16(c.op, prec == HX_BF16_SPLIT, x, y, c.s);
   ApplyArgs a{c.op.mesh->idx.ptr, c.op.mesh->own.ptr, nullptr, nullptr, nullptr, x, y, nullptr, 0, 0,
               c.op.mesh->nnodes};
   if (c.op.mesh->nuntouched > 0) HX_HIP(hipMemsetAsync(y, 0, sizeof(float) * c.n, c.s));
@@ -647,15 +647,16 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   const bool cheb = o.precond == HX_PC_CHEBYSHEV || (mlp && o.fallback == HX_PC_CHEBYSHEV);
   if (cheb && (o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) || o.lanczos_steps < 2))
     return fail(HX_EINVAL, "Chebyshev needs cheb_degree >= 1, cheb_ratio > 1, lanczos_steps >= 2");
-  if (cheb && o.cheb_prec != HX_FP64 && o.cheb_prec != HX_FP32 && o.cheb_prec != HX_BF16)
-    return fail(HX_EINVAL, "cheb_prec must be HX_FP64, HX_FP32 or HX_BF16");
+  const bool cheb_bf16 = o.cheb_prec == HX_BF16 || o.cheb_prec == HX_BF16_SPLIT;
+  if (cheb && o.cheb_prec != HX_FP64 && o.cheb_prec != HX_FP32 && !cheb_bf16)
+    return fail(HX_EINVAL, "cheb_prec must be HX_FP64, HX_FP32, HX_BF16 or HX_BF16_SPLIT");
   if (o.mode == HX_SOLVE_IR && (!(o.inner_rtol > 0 && o.inner_rtol < 1) || o.inner_maxit < 1))
     return fail(HX_EINVAL, "IR needs 0 < inner_rtol < 1 and inner_maxit >= 1");
   if (o.mode == HX_SOLVE_IR && o.inner_qdata != HX_FP64 && o.inner_qdata != HX_FP32)
     return fail(HX_EINVAL, "inner_qdata must be HX_FP64 or HX_FP32");
   if (o.mode == HX_SOLVE_IR && cheb && o.cheb_prec == HX_FP64)
-    return fail(HX_EINVAL, "the IR inner solve runs in FP32: cheb_prec must be HX_FP32 or HX_BF16");
-  if (cheb && o.cheb_prec == HX_BF16 && (op->kind != HX_DIFFUSION || op->ncomp != 1))
+    return fail(HX_EINVAL, "the IR inner solve runs in FP32: cheb_prec must be HX_FP32, HX_BF16 or HX_BF16_SPLIT");
+  if (cheb && cheb_bf16 && (op->kind != HX_DIFFUSION || op->ncomp != 1))
     return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
   *info = hx_solve_info{};
   hipStream_t s = static_cast<hipStream_t>(stream);

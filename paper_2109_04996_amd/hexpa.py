@@ -19,7 +19,7 @@ HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOW
     0, -1, -2, -3, -4, -5, -6, -7, -8
 HX_GAUSS, HX_GLL = 0, 1
 HX_MASS, HX_DIFFUSION = 0, 1
-HX_FP64, HX_FP32, HX_BF16 = 0, 1, 2
+HX_FP64, HX_FP32, HX_BF16, HX_BF16_SPLIT = 0, 1, 2, 3
 HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP = 0, 1, 2, 3
 HX_SOLVE_FP64, HX_SOLVE_IR = 0, 1
 
@@ -93,7 +93,7 @@ SIGNATURES = [
     ("hx_op_create", C.c_int, [_VP, _VP, C.c_int, C.c_int, C.POINTER(hx_kappa_rff), _VP, C.POINTER(_VP)]),
     ("hx_op_apply", C.c_int, [_VP, _VP, _VP, _VP]),
     ("hx_op_apply_f32", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
-    ("hx_op_apply_bf16", C.c_int, [_VP, _VP, _VP, _VP]),
+    ("hx_op_apply_bf16", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("hx_op_apply_elem", C.c_int, [_VP, _VP, _VP, _VP]),
     ("hx_op_diagonal", C.c_int, [_VP, _VP, _VP]),
     ("hx_op_get_stats", C.c_int, [_VP, C.POINTER(hx_op_stats)]),
@@ -251,8 +251,8 @@ def hx_op_apply_f32(op, qdata_prec, x, y, stream=None):
     _check(load().hx_op_apply_f32(op, qdata_prec, _ptr(x), _ptr(y), _stream(stream)), "hx_op_apply_f32")
 
 
-def hx_op_apply_bf16(op, x, y, stream=None):
-    _check(load().hx_op_apply_bf16(op, _ptr(x), _ptr(y), _stream(stream)), "hx_op_apply_bf16")
+def hx_op_apply_bf16(op, x, y, stream=None, prec=HX_BF16):
+    _check(load().hx_op_apply_bf16(op, prec, _ptr(x), _ptr(y), _stream(stream)), "hx_op_apply_bf16")
 
 
 def hx_op_apply_elem(op, x, y_e, stream=None):

@@ -49,9 +49,9 @@ class Problem:
         hx.hx_op_apply_f32(self.h_op, qdata_prec, x, y)
         return y
 
-    def apply_bf16(self, x, y=None):
+    def apply_bf16(self, x, y=None, prec=hx.HX_BF16):
         y = self.zeros(self.torch.float32) if y is None else y
-        hx.hx_op_apply_bf16(self.h_op, x, y)
+        hx.hx_op_apply_bf16(self.h_op, x, y, prec=prec)
         return y
 
     def apply_elem(self, x):

@@ -114,11 +114,12 @@ def test_failures_reported():
 
 
 @pytest.mark.parametrize("mode", [hx.HX_SOLVE_FP64, hx.HX_SOLVE_IR])
-def test_chebyshev_bf16_flexible(mode):
+@pytest.mark.parametrize("prec", [hx.HX_BF16, hx.HX_BF16_SPLIT])
+def test_chebyshev_bf16_flexible(mode, prec):
     mesh, pr, b, A, bo, free = _setup(4, 6, 8, "gauss", warp="B")
     with pr:
         _, ij = pr.solve(b, rtol=1e-8)
-        x, info = pr.solve(b, rtol=1e-8, mode=mode, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_BF16, flexible=1)
+        x, info = pr.solve(b, rtol=1e-8, mode=mode, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=prec, flexible=1)
         assert info["true_rel_residual"] <= 1.05e-8, info
         assert info["iterations"] < ij["iterations"], (info, ij)
         xd = solvers.direct_solve(A, bo, free)

@@ -118,3 +118,32 @@ def test_strip_apply_matches_evector_sum(N, frac, kind, rule, q):
         assert err <= 1e-13, err
         # the strip path is deterministic
         assert torch.equal(y, pr.apply(x))
+
+
+@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
+def test_full_size_sampled_nodes_match_oracle(kind, rule, q):
+    """The benchmark workload (mesh A, 48^3 elements shuffled with seed 0, x ~ U[-1,1] from seed 1,
+    38.3M DOFs) through the strip launches the benchmark times, checked against the oracle at every
+    node of 16 seeded elements: interior, face, edge and corner nodes, strip ends among them. Each
+    reference value sums the oracle's dense element matrices of all elements holding the node."""
+    p, N = 7, 48
+    print(f"\n[case] full size N={N} p={p} q={q} {kind} sampled nodes", flush=True)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    en = mesh["elem_nodes"]
+    x = uniform_vector(mesh["nnodes"], 1)
+    with Problem(N, p, q, rule, kind, mesh=mesh) as pr:
+        assert pr.stats["nstrips"] == 13824 and pr.stats["nstrip_colors"] == 8
+        y = pr.apply(pr.to_dev(x)).cpu().numpy()
+    rng = np.random.default_rng(5)
+    sel = rng.choice(mesh["nelem"], 16, replace=False)
+    targets = np.unique(en[sel].ravel())
+    touch = np.flatnonzero(np.isin(en, targets).any(axis=1))
+    Ae = fem.element_matrices(mesh, p, q, rule, kind, None, touch)
+    xe = x[en[touch].astype(np.int64)]
+    yref = np.zeros(mesh["nnodes"])
+    babs = np.zeros(mesh["nnodes"])
+    np.add.at(yref, en[touch].ravel(), np.einsum("eij,ej->ei", Ae, xe).ravel())
+    np.add.at(babs, en[touch].ravel(), np.einsum("eij,ej->ei", np.abs(Ae), np.abs(xe)).ravel())
+    err = rel(y[targets], yref[targets])
+    assert err <= 1e-12, err
+    assert np.max(np.abs(y[targets] - yref[targets])) <= 1e-12 * babs[targets].max()
