@@ -346,6 +346,9 @@ def main():
                     help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
+    ap.add_argument("--pmc-kernels", action="store_true",
+                    help="short run for the FLOP-rate counter pass: 4 applies of each hot kernel (BP5 p=7 FP64 and "
+                         "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build measures the single-GPU "
@@ -371,6 +374,31 @@ def main():
     n, E = mesh["nnodes"], mesh["nelem"]
     x = pr.to_dev(uniform_vector(n, 1))
     y = pr.zeros()
+    if a.pmc_kernels:
+        from paper_2109_04996_amd import hexpa as hxm
+        for _ in range(4):
+            pr.apply(x, y)
+        x32, y32 = x.float(), pr.zeros(torch.float32)
+        for _ in range(4):
+            pr.apply_f32(x32, hxm.HX_FP32, y32)
+        pr.close()
+        mesh6 = lattice_mesh(48, 6, warp="A", shuffle_seed=0)
+        with Problem(48, 6, 8, "gauss", "diffusion", mesh=mesh6) as p6:
+            x6 = p6.to_dev(uniform_vector(mesh6["nnodes"], 1))
+            y6 = p6.zeros()
+            x6f, y6f = x6.float(), p6.zeros(torch.float32)
+            for _ in range(4):
+                p6.apply(x6, y6)
+            for _ in range(4):
+                p6.apply_f32(x6f, hxm.HX_FP32, y6f)
+            for prec in (hxm.HX_BF16, hxm.HX_BF16_SPLIT):
+                for _ in range(4):
+                    p6.apply_bf16(x6f, y6f, prec=prec)
+            torch.cuda.synchronize()
+        print(json.dumps(dict(pmc_kernels=True, workloads=["bp5_p7_n48 FP64 and FP32",
+                                                           "p6_q8_gauss_n48 FP64, FP32, bf16, bf16 split"])),
+              flush=True)
+        return
     if a.pmc_run:
         # reference copy of known size (1 GiB read + 1 GiB written) for scaling the counters
         ref_a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
