@@ -64,9 +64,14 @@ __device__ __forceinline__ int xcd_item(int bid, int G) {
   return xcd * base + (xcd < rem ? xcd : rem) + loc;
 }
 
-template <typename TQ, typename T>
+// qdata loads: streaming (nontemporal) for one component; cached for several, whose workgroups
+// (adjacent work items on one XCD) read the same qdata
+template <int NC, typename TQ, typename T>
 __device__ __forceinline__ T ld_q(const TQ *p) {
-  return static_cast<T>(__builtin_nontemporal_load(p));
+  if constexpr (NC > 1)
+    return static_cast<T>(*p);
+  else
+    return static_cast<T>(__builtin_nontemporal_load(p));
 }
 
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
@@ -133,8 +138,8 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
             ut += tD[k * P + l] * u[l];
           }
           const TQ *g = qe + k * 6 * Q2;
-          const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q2), g2 = ld_q<TQ, T>(g + 2 * Q2);
-          const T g3 = ld_q<TQ, T>(g + 3 * Q2), g4 = ld_q<TQ, T>(g + 4 * Q2), g5 = ld_q<TQ, T>(g + 5 * Q2);
+          const T g0 = ld_q<NC, TQ, T>(g), g1 = ld_q<NC, TQ, T>(g + Q2), g2 = ld_q<NC, TQ, T>(g + 2 * Q2);
+          const T g3 = ld_q<NC, TQ, T>(g + 3 * Q2), g4 = ld_q<NC, TQ, T>(g + 4 * Q2), g5 = ld_q<NC, TQ, T>(g + 5 * Q2);
           B[k * P2 + b * P + a] = g0 * ur + g1 * us + g2 * ut;
           C[k * P2 + b * P + a] = g1 * ur + g3 * us + g4 * ut;
           const T vt = g2 * ur + g4 * us + g5 * ut;
@@ -195,7 +200,7 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
       T w[Q];
       if constexpr (MODE == MODE_MASS) {
 #pragma unroll
-        for (int cq = 0; cq < Q; ++cq) w[cq] = live ? uq[cq] * ld_q<TQ, T>(qe + cq * Q2) : T(0);
+        for (int cq = 0; cq < Q; ++cq) w[cq] = live ? uq[cq] * ld_q<NC, TQ, T>(qe + cq * Q2) : T(0);
       } else {
 #pragma unroll
         for (int cq = 0; cq < Q; ++cq) C[cq * Q2 + b * Q + a] = uq[cq];
@@ -213,8 +218,8 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
               ut += tD[cq * Q + l] * uq[l];
             }
             const TQ *g = qe + cq * 6 * Q2;
-            const T g0 = ld_q<TQ, T>(g), g1 = ld_q<TQ, T>(g + Q2), g2 = ld_q<TQ, T>(g + 2 * Q2);
-            const T g3 = ld_q<TQ, T>(g + 3 * Q2), g4 = ld_q<TQ, T>(g + 4 * Q2), g5 = ld_q<TQ, T>(g + 5 * Q2);
+            const T g0 = ld_q<NC, TQ, T>(g), g1 = ld_q<NC, TQ, T>(g + Q2), g2 = ld_q<NC, TQ, T>(g + 2 * Q2);
+            const T g3 = ld_q<NC, TQ, T>(g + 3 * Q2), g4 = ld_q<NC, TQ, T>(g + 4 * Q2), g5 = ld_q<NC, TQ, T>(g + 5 * Q2);
             A[cq * Q2 + b * Q + a] = g0 * ur + g1 * us + g2 * ut;
             B[cq * Q2 + b * Q + a] = g1 * ur + g3 * us + g4 * ut;
             const T vt = g2 * ur + g4 * us + g5 * ut;

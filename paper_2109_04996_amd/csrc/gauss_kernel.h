@@ -189,7 +189,7 @@ __device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict_
       const TQ *const ql = qd + e * Q3 + b * Q2 + a * Q;
       T v[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) v[q] = ul[q] * (T)__builtin_nontemporal_load(ql + q);
+      for (int q = 0; q < Q; ++q) v[q] = ul[q] * ld_q<NC, TQ, T>(ql + q);
       // transposed interpolation along r1 straight from registers: S0[i][qj][qk]
       T z[P];
       interp_bwd<P, Q, T>(tI, v, z);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict_
       T ga[6], gb[6];
       auto load_plane = [&](T(&g)[6], int k) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * Q2);
+        for (int m = 0; m < 6; ++m) g[m] = ld_q<NC, TQ, T>(qe + (k * 6 + m) * Q2);
       };
       load_plane(ga, 0);
       load_plane(gb, 1);

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kStrip * 64)
   T ga[6], gb[6];
   auto load_plane = [&](T(&g)[6], int k) {
 #pragma unroll
-    for (int m = 0; m < 6; ++m) g[m] = (T)__builtin_nontemporal_load(qe + (k * 6 + m) * P2);
+    for (int m = 0; m < 6; ++m) g[m] = ld_q<NC, TQ, T>(qe + (k * 6 + m) * P2);
   };
 
   {
