@@ -14,7 +14,7 @@ namespace hx {
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
   // strips (one workgroup per strip and component)
-  if constexpr (MODE == MODE_COLLOC && P == kStripP && !EOUT) {
+  if constexpr (MODE == MODE_COLLOC && strip_degree(P) && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
     if (m.nstrips > 0) {
       // strip scatter: one launch per strip color
@@ -22,7 +22,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
       for (int c = 0; c < m.nstrip_colors; ++c) {
         const int64_t s0 = m.strip_color_start[c], s1 = m.strip_color_start[c + 1];
         if (s1 <= s0) continue;
-        const dim3 grid((unsigned)((s1 - s0) * NC)), block(kStrip * 64);
+        const dim3 grid((unsigned)((s1 - s0) * NC)), block(StripCfg<P>::NW * 64);
         if (m.idx_affine.ptr)
           hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr, qd,
                              tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);

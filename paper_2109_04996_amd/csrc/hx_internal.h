@@ -12,8 +12,14 @@
 namespace hx {
 
 constexpr int kMaxP = 9;   // nodes per direction (degree 8)
-constexpr int kStrip = 8;  // elements per strip (one wavefront each) in the strip-scatter collocated kernel
-constexpr int kStripP = 8; // strips are built for this many nodes per direction (degree 7)
+constexpr int kStrip = 8;  // longest strip (elements): the stride of the strip element lists
+constexpr int kStripP = 8; // the Gauss-point mass kernel uses strips at this many nodes per direction
+// strips are built for P = 3, 4, 5 and 8 nodes per direction: an element's P^2 lines must fit one
+// wavefront, and at P = 6 and 7 (one element per wavefront with 28 and 15 lanes idle) the
+// one-element-per-workgroup kernel measured faster
+constexpr bool strip_degree(int P) { return (P >= 3 && P <= 5) || P == 8; }
+// elements per strip for P nodes per direction: seven for P = 3 (they fill one wavefront), else kStrip
+constexpr int strip_len(int P) { return P == 3 ? 7 : kStrip; }
 constexpr int kMaxQ = 10;  // quadrature points per direction
 
 // ---------------------------------------------------------------- errors
@@ -94,7 +100,7 @@ struct hx_mesh_s {
   // strips: chains of up to kStrip elements, each sharing its r1 = +1 face with the next one's
   // r1 = -1 face, scattered together by one workgroup of the collocated kernel. Strips have
   // their own coloring (no two strips of a color share a node) and ownership bits; element ids
-  // are internal positions. Empty unless P == kStripP and the mesh has such chains.
+  // are internal positions. Empty unless strip_degree(P) and the mesh has such chains.
   int nstrip_colors = 0;
   int64_t nstrips = 0;
   std::vector<int64_t> strip_color_start;  // nstrip_colors + 1, in strips

@@ -116,7 +116,7 @@ int greedy_color(int P3, int64_t nnodes, const int32_t *en, const std::vector<in
 
 // Strips for the strip-scatter collocated kernel (see hx_mesh_s). Element u follows t when u's
 // nodes (0, j, k) are t's nodes (p, j, k) for every (j, k): the two share t's r1 = +1 face with
-// matching in-face orientation. Chains of followers are cut into strips of at most kStrip
+// matching in-face orientation. Chains of followers are cut into strips of at most strip_len(P)
 // elements; the strips are colored greedily over the union of their nodes (keeping the fewer
 // colors of a Morton and a row visiting order) and ordered like the elements. Inside a strip,
 // element w > 0 does not write its r1 = -1 face (element w-1 writes the shared face after adding
@@ -153,7 +153,7 @@ bool build_strips(hx_mesh_s &m, const std::vector<int32_t> &idx, const std::vect
     for (int32_t u = t0; u != -1 && !vis[u]; u = nxt[u]) {
       vis[u] = 1;
       s.push_back(u);
-      if ((int)s.size() == hx::kStrip) {
+      if ((int)s.size() == hx::strip_len(P)) {
         strips.push_back(s);
         s.clear();
       }
@@ -451,11 +451,11 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
     }
   }
 
-  // strips for the strip-scatter kernel (degree 7 only)
+  // strips for the strip-scatter kernels
   std::vector<int32_t> selems;
   std::vector<uint16_t> sown;
   bool strips = false;
-  if (P == hx::kStripP) {
+  if (hx::strip_degree(P)) {
     std::vector<uint64_t> mk_int(nelem);
     std::vector<int64_t> rk_int(nelem * 3);
     for (int64_t t = 0; t < nelem; ++t) {

@@ -1,21 +1,23 @@
-// Collocated diffusion apply with a strip scatter (degree 7, P = 8 nodes per direction).
+// Collocated diffusion apply with a strip scatter (P = p + 1 = 3, 4, 5 or 8 nodes per direction).
 //
-// The operator and the per-element work are those of k_colloc (colloc_kernel.h): one wavefront
-// per element, a thread per line, LDS transposes, the even-odd derivative. What changes is the
-// scatter G^T (libCEED section: G^T sums the element contributions into the L-vector). A
-// workgroup takes a strip of up to kStrip elements that follow each other along r1 (element
-// w+1's r1 = -1 face is element w's r1 = +1 face, built by the mesh), one wavefront each:
+// The operator and the per-element work are those of k_colloc (colloc_kernel.h): a thread per
+// line, LDS transposes, the even-odd derivative, and as many elements per wavefront as their
+// P^2 lines fit (one for P = 8, two for P = 5, four for P = 4, seven for P = 3). What changes
+// is the scatter G^T (libCEED section: G^T sums the element contributions
+// into the L-vector). A workgroup takes a strip of up to StripCfg<P>::SL elements that follow
+// each other along r1 (element w+1's r1 = -1 face is element w's r1 = +1 face, built by the
+// mesh):
 //
 // * the shared faces are summed in LDS: element w+1 leaves its face values there, element w adds
 //   them to its own and writes the node once -- no read-modify-write and no second store;
-// * the r1-rows of a strip's elements join into rows of up to 8*7+1 consecutive nodes, written by
-//   one workgroup within its lifetime, so the partially covered memory sectors of a row are
+// * the r1-rows of a strip's elements join into rows of up to SL*p+1 consecutive nodes, written
+//   by one workgroup within its lifetime, so the partially covered memory sectors of a row are
 //   those at its two ends, not those at every element boundary;
 // * strips have their own coloring (no two strips of a color share a node), one launch per
 //   color, and their own ownership bits: the first writer of a node in strip order stores it,
 //   later writers read-modify-write it.
 //
-// Each wavefront's LDS buffers are its own, so the steps inside an element synchronise the
+// Each element's LDS buffers are its own, so the steps inside an element synchronise the
 // wavefront only; the face exchange is the one workgroup barrier per component.
 
 #pragma once
@@ -33,25 +35,43 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Strip shape for P nodes per direction: EPW elements per wavefront, SL elements per strip
+// (at most kStrip, the stride of the strip element lists), NW wavefronts per workgroup.
+template <int P>
+struct StripCfg {
+  static constexpr int P2 = P * P;
+  static constexpr int EPW = P2 <= 64 ? 64 / P2 : 1;
+  static constexpr int SL = strip_len(P);
+  static constexpr int NW = (SL + EPW - 1) / EPW;
+  static_assert(SL <= kStrip, "strip longer than the element list stride");
+  static_assert(P2 <= 64, "an element's lines must fit one wavefront");
+};
+
 // One workgroup per (strip, component) of color [s_begin, s_begin + gridDim.x / NC); strip s's elements are
 // selems[s][0..len) (internal positions), -1 past the end. IDX: 0 one node id per element node,
 // 1 one per r1-row (ROWS of k_colloc), 2 {base, s_j, s_k} per element, read with scalar loads
 // (node (i, j, k) = base + i + j s_j + k s_k), so the gather does not wait on a vector load.
 // sown: the strip-order ownership bits of each element.
 template <int P, int NC, typename T, typename TQ, int IDX>
-__global__ void __launch_bounds__(kStrip * 64)
+__global__ void __launch_bounds__(StripCfg<P>::NW * 64)
     k_colloc_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                    const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y,
                    const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
-  static_assert(P * P == 64, "one element per wavefront");
-  constexpr int P2 = P * P, P3 = P2 * P, LS = P + 1, PL = P * LS, BUF = P * PL;
-  __shared__ T s0[kStrip][BUF];
-  __shared__ T s1[kStrip][BUF];
-  __shared__ T face[kStrip][P2];  // element w's r1 = -1 face, [k][j]
+  using SC = StripCfg<P>;
+  constexpr int P2 = P * P, P3 = P2 * P, LS = P + 1, PL = P * LS, BUF = P * PL, SL = SC::SL, EPW = SC::EPW;
+  __shared__ T s0[SL][BUF];
+  __shared__ T s1[SL][BUF];
+  __shared__ T face[SL][P2];  // element w's r1 = -1 face, [k][j]
 
   const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lt = tid & 63;  // w is wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;  // wv is wave-uniform
+  const int sw = l64 / P2, lt = l64 - sw * P2;  // element slot in the wavefront, line in the element
   const int a = lt % P, b = lt / P;
+  // w: the element's position in the strip; lanes past the last slot of a wavefront, or past the
+  // strip length, work on slot 0 of the strip and store nothing
+  const int wr = wv * EPW + sw;
+  const bool lane_ok = (P2 == 64 && SC::NW == SL) ? true : (sw < EPW && wr < SL);  // P = 8: every lane
+  const int w = lane_ok ? wr : 0;
   // one component of one strip per block: consecutive blocks take consecutive (spatially sorted)
   // strips; with several components, an XCD-aware order keeps a strip's components on one XCD
   const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -59,10 +79,10 @@ __global__ void __launch_bounds__(kStrip * 64)
   const int64_t s = s_begin + sl;
   const int32_t *const se = selems + s * kStrip;
   const int32_t el = se[w];
-  const bool live = el >= 0;
-  const int64_t ee = live ? el : se[0];  // a slot past the strip's end works on a valid element
+  const bool live = el >= 0 && lane_ok;
+  const int64_t ee = el >= 0 ? el : se[0];  // a slot past the strip's end works on a valid element
   const bool has_prev = live && w > 0;
-  const bool has_next = (w + 1 < kStrip) && se[w < kStrip - 1 ? w + 1 : w] >= 0 && live;
+  const bool has_next = live && (w + 1 < SL) && se[w < SL - 1 ? w + 1 : w] >= 0;
   // this lane's nodes are written by the previous element of the strip
   const bool skip = has_prev && a == 0;
   T *const S0 = s0[w];
@@ -92,6 +112,9 @@ __global__ void __launch_bounds__(kStrip * 64)
 #pragma unroll
     for (int m = 0; m < 6; ++m) g[m] = ld_q<NC, TQ, T>(qe + (k * 6 + m) * P2);
   };
+  // a lane that is not on a live element only reads (its slot-0 or padding element's data): it
+  // never writes an LDS slot another lane uses
+  const bool lds_ok = lane_ok;
 
   {
     // ---- lines along r3: thread (i=a, j=b). Gather, and the r3 derivative in registers.
@@ -103,8 +126,10 @@ __global__ void __launch_bounds__(kStrip * 64)
       load_plane(ga, 0);
       load_plane(gb, 1);
       __builtin_amdgcn_sched_barrier(0);
+      if (lds_ok) {
 #pragma unroll
-      for (int k = 0; k < P; ++k) S0[AT(a, b, k)] = u[k];
+        for (int k = 0; k < P; ++k) S0[AT(a, b, k)] = u[k];
+      }
       eo_apply<P, T>(C, u, ut);
     }
     wave_sync();
@@ -120,11 +145,15 @@ __global__ void __launch_bounds__(kStrip * 64)
     {
       T r[P];
       eo_apply<P, T>(C, li, r);
+      if (lds_ok) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+        for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+      }
       eo_apply<P, T>(C, lj, r);
+      if (lds_ok) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+        for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+      }
     }
     wave_sync();
     // ---- pointwise: (vr, vs, vt) = G (ur, us, ut) on lines along r3 (thread (i=a, j=b))
@@ -133,8 +162,10 @@ __global__ void __launch_bounds__(kStrip * 64)
     for (int k = 0; k < P; ++k) {
       T(&g)[6] = (k & 1) ? gb : ga;
       const T ur = S0[AT(a, b, k)], us = S1[AT(a, b, k)];
-      S0[AT(a, b, k)] = g[0] * ur + g[1] * us + g[2] * ut[k];
-      S1[AT(a, b, k)] = g[1] * ur + g[3] * us + g[4] * ut[k];
+      if (lds_ok) {
+        S0[AT(a, b, k)] = g[0] * ur + g[1] * us + g[2] * ut[k];
+        S1[AT(a, b, k)] = g[1] * ur + g[3] * us + g[4] * ut[k];
+      }
       vt[k] = g[2] * ur + g[4] * us + g[5] * ut[k];
       if (k + 2 < P) load_plane(g, k + 2);
       __builtin_amdgcn_sched_barrier(0);
@@ -157,11 +188,15 @@ __global__ void __launch_bounds__(kStrip * 64)
     {
       T r[P];
       eo_apply_t<P, T>(C, li, r);
+      if (lds_ok) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+        for (int i = 0; i < P; ++i) S0[AT(i, a, b)] = r[i];
+      }
       eo_apply_t<P, T>(C, lj, r);
+      if (lds_ok) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+        for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = r[j];
+      }
     }
     wave_sync();
     // ---- element sums on lines along r3; shared faces through LDS; scatter
@@ -172,7 +207,10 @@ __global__ void __launch_bounds__(kStrip * 64)
 #pragma unroll
       for (int k = 0; k < P; ++k) face[w][k * P + b] = out[k];
     }
-    __syncthreads();
+    if constexpr (SC::NW > 1)
+      __syncthreads();
+    else
+      wave_sync();
     if (has_next && a == P - 1) {
 #pragma unroll
       for (int k = 0; k < P; ++k) out[k] += face[w + 1][k * P + b];

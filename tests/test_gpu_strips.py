@@ -1,4 +1,4 @@
-"""GPU tests of the strip scatter of the degree-7 applies (collocated diffusion, Gauss-point mass).
+"""GPU tests of the strip scatter (collocated diffusion at every degree p >= 2, Gauss-point mass at p = 7).
 
 The strip kernels scatter chains of face-adjacent elements together. Their results are checked
 against the FP64 oracle on meshes whose elements have random proper rotations (so chains break
@@ -57,20 +57,22 @@ def rotate_elements(mesh, p, frac, seed):
     return out
 
 
-def test_strips_are_built_for_degree_7_only():
-    mesh = lattice_mesh(4, 7, warp="A", shuffle_seed=3)
-    with Problem(4, 7, 8, "gll", "diffusion", mesh=mesh) as pr:
-        assert pr.stats["nstrips"] == 16  # chains of 4 along r1
-        assert pr.stats["nstrip_colors"] >= 2
-    mesh = lattice_mesh(4, 4, warp="A", shuffle_seed=3)
-    with Problem(4, 4, 5, "gll", "diffusion", mesh=mesh) as pr:
-        assert pr.stats["nstrips"] == 0
+@pytest.mark.parametrize("p,N,nstrips", [(7, 4, 16), (4, 4, 16), (2, 4, 16), (3, 4, 16), (4, 9, 162), (2, 9, 162),
+                                         (1, 4, 0), (5, 4, 0), (6, 4, 0), (8, 4, 0)])
+def test_strip_counts(p, N, nstrips):
+    # chains of N elements along r1, cut into strips of 8 (7 at p = 2); strips at p = 2, 3, 4 and 7 only
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=3)
+    with Problem(N, p, p + 1, "gll", "diffusion", mesh=mesh) as pr:
+        assert pr.stats["nstrips"] == nstrips
+        if nstrips:
+            assert pr.stats["nstrip_colors"] >= 2
 
 
-@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
+@pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
+                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3)])
 @pytest.mark.parametrize("ncomp", [1, 3])
-def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, q):
-    p, N = 7, 4
+def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, p, q):
+    N = 4 if p > 2 else 6
     print(f"\n[case] strips rotated N={N} p={p} q={q} {kind} ncomp={ncomp}", flush=True)
     mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=5), p, 0.15, seed=ncomp)
     A = fem.assemble(mesh, p, q, rule, kind)
@@ -99,11 +101,11 @@ def _scatter_evector(pr, ye):
     return y
 
 
-@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
+@pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
+                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3)])
 @pytest.mark.parametrize("N,frac", [(9, 0.0), (9, 0.2), (48, 0.0)])
-def test_strip_apply_matches_evector_sum(N, frac, kind, rule, q):
-    # N = 9: chains of 9 cut into 8 + 1; N = 48: the benchmark mesh (6 strips of 8 per chain)
-    p = 7
+def test_strip_apply_matches_evector_sum(N, frac, kind, rule, p, q):
+    # N = 9: chains of 9 cut into 8 + 1 (7 + 2 at p = 2); N = 48: the benchmark mesh
     print(f"\n[case] strips vs E-vector N={N} frac={frac} {kind} q={q}", flush=True)
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
     if frac > 0:
