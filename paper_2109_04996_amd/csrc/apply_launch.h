@@ -14,7 +14,7 @@ namespace hx {
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
   // strips (one workgroup per strip and component)
-  if constexpr (MODE == MODE_COLLOC && strip_degree(P) && !EOUT) {
+  if constexpr (MODE == MODE_COLLOC && colloc_strips(P) && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
     if (m.nstrips > 0) {
       // strip scatter: one launch per strip color
@@ -65,8 +65,8 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // that kernel fills its wavefronts with several elements and wins
   constexpr bool kGauss = std::is_same<T, double>::value && Q <= 9 && !EOUT &&
                           ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
-  if constexpr (kGauss && MODE == MODE_MASS && P == kStripP) {
-    // degree-7 mass on a mesh with strips: the strip scatter
+  if constexpr (kGauss && gauss_strips(P, Q, MODE == MODE_MASS, NC)) {
+    // on a mesh with strips: the strip scatter
     const hx_mesh_s &m = *op.mesh;
     if (m.nstrips > 0) {
       const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);

@@ -14,10 +14,17 @@ namespace hx {
 constexpr int kMaxP = 9;   // nodes per direction (degree 8)
 constexpr int kStrip = 8;  // longest strip (elements): the stride of the strip element lists
 constexpr int kStripP = 8; // the Gauss-point mass kernel uses strips at this many nodes per direction
-// strips are built for P = 3, 4, 5 and 8 nodes per direction: an element's P^2 lines must fit one
-// wavefront, and at P = 6 and 7 (one element per wavefront with 28 and 15 lanes idle) the
-// one-element-per-workgroup kernel measured faster
-constexpr bool strip_degree(int P) { return (P >= 3 && P <= 5) || P == 8; }
+// Strip scatter (an element's P^2 node lines must fit one wavefront). The collocated kernel uses
+// strips at P = 3, 4, 5 and 8 nodes per direction: at P = 6 and 7 (one element per wavefront
+// with 28 and 15 lanes idle) the one-element-per-workgroup kernel measured faster. The Gauss-point
+// kernel uses them for mass at P = 8 and for scalar diffusion with q = 8 at P = 7 and 8 (its 166
+// registers allow one eight-wavefront workgroup per CU, against twelve one-wavefront ones without
+// strips: p = 7 gains 9%, p = 6 1.5%, and three components lose 1.5%).
+constexpr bool colloc_strips(int P) { return (P >= 3 && P <= 5) || P == 8; }
+constexpr bool gauss_strips(int P, int Q, bool mass, int NC) {
+  return mass ? P == 8 : (NC == 1 && Q == 8 && (P == 7 || P == 8));
+}
+constexpr bool strip_degree(int P) { return colloc_strips(P) || P == 7; }  // the mesh builds strips
 // elements per strip for P nodes per direction: seven for P = 3 (they fill one wavefront), else kStrip
 constexpr int strip_len(int P) { return P == 3 ? 7 : kStrip; }
 constexpr int kMaxQ = 10;  // quadrature points per direction

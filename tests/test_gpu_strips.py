@@ -57,10 +57,10 @@ def rotate_elements(mesh, p, frac, seed):
     return out
 
 
-@pytest.mark.parametrize("p,N,nstrips", [(7, 4, 16), (4, 4, 16), (2, 4, 16), (3, 4, 16), (4, 9, 162), (2, 9, 162),
-                                         (1, 4, 0), (5, 4, 0), (6, 4, 0), (8, 4, 0)])
+@pytest.mark.parametrize("p,N,nstrips", [(7, 4, 16), (4, 4, 16), (2, 4, 16), (3, 4, 16), (6, 4, 16), (4, 9, 162),
+                                         (2, 9, 162), (1, 4, 0), (5, 4, 0), (8, 4, 0)])
 def test_strip_counts(p, N, nstrips):
-    # chains of N elements along r1, cut into strips of 8 (7 at p = 2); strips at p = 2, 3, 4 and 7 only
+    # chains of N elements along r1, cut into strips of 8 (7 at p = 2); strips at p = 2, 3, 4, 6 and 7 only
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=3)
     with Problem(N, p, p + 1, "gll", "diffusion", mesh=mesh) as pr:
         assert pr.stats["nstrips"] == nstrips
@@ -69,7 +69,8 @@ def test_strip_counts(p, N, nstrips):
 
 
 @pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
-                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3)])
+                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3),
+                                           ("diffusion", "gauss", 6, 8), ("diffusion", "gauss", 7, 8)])
 @pytest.mark.parametrize("ncomp", [1, 3])
 def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, p, q):
     N = 4 if p > 2 else 6
@@ -102,7 +103,8 @@ def _scatter_evector(pr, ye):
 
 
 @pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
-                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3)])
+                                           ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3),
+                                           ("diffusion", "gauss", 6, 8)])
 @pytest.mark.parametrize("N,frac", [(9, 0.0), (9, 0.2), (48, 0.0)])
 def test_strip_apply_matches_evector_sum(N, frac, kind, rule, p, q):
     # N = 9: chains of 9 cut into 8 + 1 (7 + 2 at p = 2); N = 48: the benchmark mesh
