@@ -16,7 +16,9 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // strips (one workgroup per strip and component)
   if constexpr (MODE == MODE_COLLOC && colloc_strips(P) && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
-    if (m.nstrips > 0) {
+    // below degree 7 a strip workgroup has 1-4 wavefronts: a launch needs two strips per CU on
+    // average to fill the chip, else the element kernel (more, smaller workgroups) is faster
+    if (m.nstrips > 0 && (P == kStripP || m.nstrips >= (int64_t)kMinStripsPerColor * m.nstrip_colors)) {
       // strip scatter: one launch per strip color
       const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
       for (int c = 0; c < m.nstrip_colors; ++c) {

@@ -25,6 +25,7 @@ constexpr bool gauss_strips(int P, int Q, bool mass, int NC) {
   return mass ? P == 8 : (NC == 1 && Q == 8 && (P == 7 || P == 8));
 }
 constexpr bool strip_degree(int P) { return colloc_strips(P) || P == 7; }  // the mesh builds strips
+constexpr int kMinStripsPerColor = 512;  // collocated strips below P = 8: at least this many per color on average
 // elements per strip for P nodes per direction: seven for P = 3 (they fill one wavefront), else kStrip
 constexpr int strip_len(int P) { return P == 3 ? 7 : kStrip; }
 constexpr int kMaxQ = 10;  // quadrature points per direction
