@@ -248,11 +248,11 @@ SWEEP = [  # (label, kind, rule, p, q, ncomp, N list)
     ("BP5", "diffusion", "gll", 7, 8, 1, (15, 20, 28, 36, 44, 48)),
     ("BP5", "diffusion", "gll", 4, 5, 1, (25, 45, 65, 85)),
     ("BP5", "diffusion", "gll", 2, 3, 1, (50, 110, 170)),
-    ("BP1", "mass", "gauss", 7, 9, 1, (48,)),
-    ("BP1", "mass", "gauss", 4, 6, 1, (85,)),
-    ("BP1", "mass", "gauss", 2, 4, 1, (170,)),
+    ("BP1", "mass", "gauss", 7, 9, 1, (15, 20, 28, 36, 44, 48)),
+    ("BP1", "mass", "gauss", 4, 6, 1, (25, 45, 65, 85)),
+    ("BP1", "mass", "gauss", 2, 4, 1, (50, 110, 170)),
     ("BP3", "diffusion", "gauss", 6, 8, 1, (48,)),
-    ("BP3", "diffusion", "gauss", 7, 9, 1, (48,)),
+    ("BP3", "diffusion", "gauss", 7, 9, 1, (15, 28, 36, 48)),
     ("BP2", "mass", "gauss", 7, 9, 3, (32,)),
     ("BP4", "diffusion", "gauss", 7, 9, 3, (32,)),
     ("BP6", "diffusion", "gll", 7, 8, 3, (32,)),
