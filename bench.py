@@ -259,6 +259,50 @@ SWEEP = [  # (label, kind, rule, p, q, ncomp, N list)
 ]
 
 
+CG_SWEEP_N = (2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48)
+
+
+def cg_sweep(label="BP5", p=7, q=8, rule="gll", Ns=CG_SWEEP_N, short=20, long=60):
+    """Throughput per CG iteration against problem size (the strong-scale limit on one GPU):
+    FP64 Jacobi-PCG on BP5 (q = p+1 GLL) or BP3 (q = p+2 Gauss), mesh A, Dirichlet, b a seeded
+    random vector on the free nodes,
+    timed as the difference of a long and a short run, so the setup, the first residual and the
+    final checks cancel. One JSON line per size, then r_max, n_0.8 and t_0.8 (the largest
+    throughput, the smallest n reaching 80% of it, and its time per iteration)."""
+    import numpy as np
+    import torch
+
+    from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
+    from paper_2109_04996_amd.problem import Problem
+    rows = []
+    for N in Ns:
+        mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+        with Problem(N, p, q, rule, "diffusion", mesh=mesh) as pr:
+            free = pr.to_dev((mesh["boundary"] == 0).astype(np.float64))
+            b = pr.to_dev(uniform_vector(mesh["nnodes"], 2)) * free
+            t = {}
+            for k in (short, long):
+                best = None
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    x, info = pr.solve(b, rtol=1e-30, maxit=k, check_every=k, raise_on_error=False)
+                    if info["iterations"] != k:
+                        raise RuntimeError(f"CG stopped after {info['iterations']} of {k} iterations at N={N}")
+                    best = info["solve_seconds"] if best is None else min(best, info["solve_seconds"])
+                t[k] = best
+            per_it = (t[long] - t[short]) / (long - short)
+            n = mesh["nnodes"]
+            rec = dict(cg_sweep=label, p=p, q=q, N=N, dofs=n, dofs_paper=mesh["nelem"] * p ** 3,
+                       us_per_iteration=round(per_it * 1e6, 2), gdofs_per_iteration=round(n / per_it / 1e9, 3))
+            rows.append(rec)
+            print(json.dumps(rec), flush=True)
+    rmax = max(r["gdofs_per_iteration"] for r in rows)
+    n08 = min((r for r in rows if r["gdofs_per_iteration"] >= 0.8 * rmax), key=lambda r: r["dofs"])
+    print(json.dumps(dict(cg_sweep_summary=label, p=p, q=q, r_max_gdofs=rmax, n_0_8=n08["dofs"],
+                          t_0_8_us=n08["us_per_iteration"],
+                          min_us_per_iteration=min(r["us_per_iteration"] for r in rows))), flush=True)
+
+
 def sweep(steps=20, warmup=3):
     """Apply throughput over the survey's size sweep and the other operator kinds: one JSON line per
     case (FP64 operator; FP32-operator figures beside it)."""
@@ -346,6 +390,8 @@ def main():
                     help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
+    ap.add_argument("--cg-sweep", action="store_true",
+                    help="throughput per Jacobi-PCG iteration against problem size (BP5 and BP3 at p=7, 3e3 to 38M DOFs)")
     ap.add_argument("--pmc-kernels", action="store_true",
                     help="short run for the FLOP-rate counter pass: 4 applies of each hot kernel (BP5 p=7 FP64 and "
                          "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
@@ -365,6 +411,10 @@ def main():
     torch.cuda.set_device(0)
     if a.sweep:
         sweep()
+        return
+    if a.cg_sweep:
+        cg_sweep("BP5", 7, 8, "gll")
+        cg_sweep("BP3", 7, 9, "gauss")
         return
     N, p = a.N, a.p
     P = Q = p + 1
