@@ -266,6 +266,14 @@ typedef struct {
                           2: cheb_degree Chebyshev steps on M A e = M r with M
                           the mode-1 map as the base (lam_max of M A from
                           lanczos_steps power iterations; FP64 operator)        */
+  int graph;           /* 1: from the second iteration on, replay each PCG
+                          iteration as a HIP graph captured once per solve, on a
+                          stream the operator owns (results identical to 0; on
+                          MI355X measured no faster: the per-iteration floor is
+                          the kernels' own boundaries, not their submission).
+                          Used when the operator needs no zero-fill of its output
+                          and the preconditioner is not HX_PC_MLP. 0: launch every
+                          kernel on the caller's stream                         */
 } hx_solve_opts;
 
 typedef struct {
@@ -287,7 +295,8 @@ typedef struct {
 /* Fill opts with defaults: FP64 Jacobi PCG, rtol 1e-8, maxit 10000,
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
  * inner_rtol 1e-4, inner_maxit 10000, FP64 inner qdata, flexible 0, no network,
- * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1. */
+ * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1,
+ * graph 0. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:

@@ -117,6 +117,13 @@ struct hx_mesh_s {
 };
 
 struct hx_op_s {
+  hx_op_s() = default;
+  hx_op_s(const hx_op_s &) = delete;
+  hx_op_s &operator=(const hx_op_s &) = delete;
+  ~hx_op_s() {
+    if (solve_stream) (void)hipStreamDestroy(solve_stream);
+  }
+  hipStream_t solve_stream = nullptr;  // the solver's own stream (graph capture), made on first use
   hx_mesh mesh = nullptr;
   hx::Basis1D b;
   int kind = 0, ncomp = 1, P = 0, Q = 0;

@@ -350,6 +350,15 @@ struct Ctx {
   double *part0, *part1, *S, *part2;
   double *hS;  // pinned host copy of S
   int applies = 0;
+  bool graph = false;  // replay PCG iterations as a captured graph
+};
+
+// Synchronises a stream when the scope ends (the solve is synchronous on every return path).
+struct StreamSync {
+  hipStream_t s = nullptr;
+  ~StreamSync() {
+    if (s) (void)hipStreamSynchronize(s);
+  }
 };
 
 #define LAUNCH_V(kern, ...) hipLaunchKernelGGL(kern, dim3(kVecBlocks), dim3(kVecThreads), 0, c.s, __VA_ARGS__)
@@ -452,7 +461,8 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
   int it = 0;
   double rr = rr0;
   T *rp = flexible ? v.rp : nullptr;
-  while (it < maxit && rr > stop2) {
+  // one iteration: kernels only, every scalar device-resident (no host work between them)
+  auto iteration = [&]() -> hx_status {
     if (hx_status st = apply_T(c, v.p, v.w, op_prec)) return st;
     LAUNCH_V((k_dot<T>), c.n, v.p, v.w, c.part0);
     FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
@@ -478,6 +488,42 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
     }
     LAUNCH_V((k_pupd<T>), c.n, c.S, v.z, v.p);
     HX_HIP(hipGetLastError());
+    return HX_OK;
+  };
+  // graph replay: captured at the second iteration (the first one, launched eagerly, makes the
+  // buffers the kernels allocate on first use) and replayed for the rest
+  hipGraphExec_t gx = nullptr;
+  struct GraphExec {
+    hipGraphExec_t &g;
+    ~GraphExec() {
+      if (g) (void)hipGraphExecDestroy(g);
+    }
+  } gx_guard{gx};
+  int graph_applies = 0;
+  while (it < maxit && rr > stop2) {
+    if (c.graph && it >= 1) {
+      if (!gx) {
+        const int applies0 = c.applies;
+        HX_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+        const hx_status st = iteration();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c.s, &g);
+        if (st != HX_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "PCG iteration capture");
+        const hipError_t ei = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return hip_fail(ei, "PCG iteration graph");
+        graph_applies = c.applies - applies0;
+        c.applies = applies0;
+      }
+      HX_HIP(hipGraphLaunch(gx, c.s));
+      c.applies += graph_applies;
+    } else {
+      if (hx_status st = iteration()) return st;
+    }
     ++it;
     if (it % check_every == 0 || it == maxit) {
       if (hx_status e = read_scalars(c)) return e;
@@ -622,6 +668,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->stall_window = 20;
   o->stall_factor = 0.1;
   o->mlp_mode = 1;
+  o->graph = 0;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -660,6 +707,17 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
   *info = hx_solve_info{};
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // graph replay needs a stream that can be captured: the solve then runs on the operator's own
+  // stream, after the caller's queued work; it is synchronous, so it has finished on return
+  const bool use_graph = o.graph != 0 && !mlp && op->mesh->nuntouched == 0;
+  StreamSync solve_done;
+  if (use_graph) {
+    if (!op->solve_stream) HX_HIP(hipStreamCreateWithFlags(&op->solve_stream, hipStreamNonBlocking));
+    HX_HIP(hipStreamSynchronize(s));
+    s = op->solve_stream;
+    stream = s;
+    solve_done.s = s;
+  }
   const int64_t n = op->mesh->nnodes * op->ncomp;
   const int NC = op->ncomp;
   const auto t_setup0 = std::chrono::steady_clock::now();
@@ -669,6 +727,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   HX_HIP(hipHostMalloc(reinterpret_cast<void **>(&hs.p), sizeof(double) * S_NSCAL));
   Ctx c{*op, s, n, NC, op->red.ptr, op->red.ptr + kVecBlocks, op->red.ptr + 3 * kVecBlocks,
         op->red.ptr + 2 * kVecBlocks, hs.p, 0};
+  c.graph = use_graph;
 
   Vecs<double> v;
   if (hx_status st = carve(op->work, n, v)) return st;

@@ -56,7 +56,7 @@ class hx_solve_opts(C.Structure):
                 ("cheb_ratio", C.c_double), ("cheb_prec", C.c_int), ("lanczos_steps", C.c_int),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
                 ("flexible", C.c_int), ("mlp", C.c_void_p), ("fallback", C.c_int), ("stall_window", C.c_int),
-                ("stall_factor", C.c_double), ("mlp_mode", C.c_int)]
+                ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int)]
 
 
 class hx_train_opts(C.Structure):

@@ -125,3 +125,21 @@ def test_chebyshev_bf16_flexible(mode, prec):
         xd = solvers.direct_solve(A, bo, free)
         xo, _, _ = solvers.jacobi_pcg(A, bo, free, tol=1e-8)
         assert np.linalg.norm(x.cpu().numpy() - xd) <= 10 * np.linalg.norm(xo - xd) + 1e-12
+
+
+@pytest.mark.parametrize("form", [dict(), dict(precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32),
+                                  dict(mode=hx.HX_SOLVE_IR),
+                                  dict(precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_BF16_SPLIT, flexible=1)])
+def test_graph_replay_matches_eager(form):
+    # the same kernels in the same order: the replayed iterations give the eager solve bit for bit,
+    # in a first solve (capture + replays) and in a second one (a new capture on the same operator),
+    # with the host's convergence checks and reads between the replays
+    mesh, pr, b, A, bo, free = _setup(4, 6, 8, "gauss", warp="B")
+    with pr:
+        x0, i0 = pr.solve(b, rtol=1e-8, check_every=3, graph=0, **form)
+        x1, i1 = pr.solve(b, rtol=1e-8, check_every=3, graph=1, **form)
+        x2, i2 = pr.solve(b, rtol=1e-8, check_every=3, graph=1, **form)
+        assert i0["iterations"] == i1["iterations"] == i2["iterations"] > 3
+        assert i0["operator_applies"] == i1["operator_applies"]
+        assert torch.equal(x0, x1) and torch.equal(x1, x2)
+        assert i1["true_rel_residual"] <= 1.05e-8
