@@ -147,3 +147,21 @@ def test_apply_bf16_matrix_cores(rule, p, q, kappa, prec):
         # the bf16 operator tracks the FP32 one as closely
         y32 = pr.apply_f32(pr.to_dev(x, torch.float32)).double().cpu().numpy()
         assert rel(y, y32) <= tol
+
+
+@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("kind,rule,p,q,ncomp", [("diffusion", "gll", 7, 8, 1), ("diffusion", "gll", 4, 5, 3),
+                                                 ("diffusion", "gll", 2, 3, 1), ("mass", "gauss", 7, 9, 1),
+                                                 ("diffusion", "gauss", 6, 8, 1), ("diffusion", "gauss", 7, 9, 3)])
+def test_smallest_meshes_match_oracle(N, kind, rule, p, q, ncomp):
+    # one element (every node on the boundary, one color, no strips) and 2^3 elements (chains of
+    # two: strips of two elements where the degree has strips), each with a single launch per
+    # color holding one workgroup
+    mesh, pr, A = _case(N, p, q, rule, kind, ncomp, seed=4)
+    with pr:
+        if N == 1:
+            assert pr.stats["nstrips"] == 0 and pr.stats["ncolors"] == 1
+        x = uniform_vector(mesh["nnodes"], 5, ncomp)
+        y = pr.apply(pr.to_dev(x)).cpu().numpy()
+        yr = fem.apply(A, x, ncomp)
+        assert rel(y, yr) <= 1e-12, rel(y, yr)
