@@ -398,8 +398,8 @@ def main():
                          "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build measures the single-GPU "
-              "path, and multi-GPU sharding is not implemented.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the library implements the single-GPU "
+              "path; multi-GPU sharding is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

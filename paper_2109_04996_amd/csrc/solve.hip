@@ -849,7 +849,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
     info->iterations = it;
     if (mlp && (result == HX_EBREAKDOWN || result == kStalled || (result == HX_OK && rre > stop2))) {
-      // judge and fallback: Jacobi or Chebyshev PCG from the current iterate, or from the iterate
+      // check and fallback: Jacobi or Chebyshev PCG from the current iterate, or from the iterate
       // before the learned phase when its correction is not finite or did not lower the true residual
       info->fallback_used = 1;
       info->fallback_reason = result == HX_EBREAKDOWN ? 1 : result == kStalled ? 2 : 3;
@@ -894,7 +894,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       const double inner_rel = std::min(0.5, std::max(o.inner_rtol, 0.5 * o.rtol * bn / rn));
       hx_status st = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, cg_prec, 1.0, inner_rel * inner_rel,
                                      o.inner_maxit, std::min(o.check_every, o.inner_maxit), o.flexible != 0, &it, &rri);
-      if (st == HX_EBREAKDOWN && it > 1) st = HX_OK;  // keep the partial correction; the FP64 residual judges it
+      if (st == HX_EBREAKDOWN && it > 1) st = HX_OK;  // keep the partial correction; the FP64 residual decides
       if (st) return st;
       inner_total += it;
       LAUNCH_V((k_axpy<float>), n, rn, v32.x, x);
