@@ -2,7 +2,9 @@
 
 A copy of ``oracle/`` is written to a temporary package with one edit (a
 transposed inverse Jacobian, a dropped determinant, a wrong sign, swapped
-derivative tables, a wrong quadrature weight, a wrong Chebyshev coefficient),
+derivative tables, a wrong quadrature weight, a wrong Chebyshev coefficient,
+a wrong multigrid correction sign, a dropped post-smoothing, wrong
+interpolation points),
 and the pin tests are run against it with the module swapped in. Every
 mutant must make at least one pin fail.
 """
@@ -26,6 +28,10 @@ MUTANTS = {
     "gll_weight_formula": ("quadrature.py", "w = 2.0 / (p * (p + 1) * Pp * Pp)", "w = 2.0 / (p * (p + 1) * Pp)"),
     "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * res)",
                               "d = rho_new * d + (2.0 * rho_new / delta) * (dinv * res)"),
+    "coarse_correction_sign": ("pmg.py", "x = x + (lv.P @ ec) * lv.f", "x = x - (lv.P @ ec) * lv.f"),
+    "dropped_post_smoothing": ("pmg.py", "return x + chebyshev_apply(lv.A, lv.dinv, t, lam_lo, lam_hi, degree)",
+                               "return x"),
+    "interpolation_swapped_nodes": ("pmg.py", "return lagrange_table(xc, xf)", "return lagrange_table(xc, -xf[::-1] ** 3)"),
 }
 
 PINS = {
@@ -33,6 +39,8 @@ PINS = {
                                    "test_diffusion_invariants", "test_collocated_diagonal_closed_form"]),
     "quadrature.py": ("test_oracle_quadrature", ["test_closed_forms", "test_exactness_degrees"]),
     "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial"]),
+    "pmg.py": ("test_oracle_pmg", ["test_interpolation_1d", "test_prolongation_reproduces_coarse_space",
+                                   "test_galerkin_identity", "test_vcycle_symmetric_and_contracting"]),
 }
 
 
