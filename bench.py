@@ -91,6 +91,33 @@ def copy_probe(nbytes=4 << 30):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def pmg_degrees(p):
+    """Halving degree schedule of the p-multigrid hierarchy: p, p // 2, ..., 1."""
+    d = [p]
+    while d[-1] > 1:
+        d.append(d[-1] // 2)
+    return d
+
+
+def pmg_hierarchy(pr, rule, warp="A", shuffle_seed=0, kappa=None, **opts):
+    """p-multigrid over ``pr`` (level 0) and coarser operators on the same lattice elements; returns
+    (handle, coarse problems, setup seconds)."""
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd.problem import Problem
+    t0 = time.perf_counter()
+    coarse = [Problem(pr.N, pc, pc + 1 if rule == "gll" else pc + 2, rule, pr.kind, warp=warp,
+                      shuffle_seed=shuffle_seed, kappa=kappa) for pc in pmg_degrees(pr.p)[1:]]
+    h = hx.hx_pmg_create([pr.h_op] + [c.h_op for c in coarse], hx.hx_pmg_opts_default(**opts))
+    return h, coarse, time.perf_counter() - t0
+
+
+def pmg_close(h, coarse):
+    from paper_2109_04996_amd import hexpa as hx
+    hx.hx_pmg_destroy(h)
+    for c in coarse:
+        c.close()
+
+
 def solves(pr, mass_pr, maxit=20000):
     """Time-to-1e-8 for plain FP64 Jacobi-PCG and the mixed-precision forms, same RHS b = B f^."""
     import numpy as np
@@ -110,6 +137,9 @@ def solves(pr, mass_pr, maxit=20000):
         "ir_fp32_cheb4": dict(mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32,
                               inner_qdata=hx.HX_FP32),
     }
+    # p-multigrid V-cycle (degrees p, p/2, ..., 1) inside flexible CG
+    mg, coarse, mg_setup = pmg_hierarchy(pr, "gll")
+    forms["fp64_fcg_pmg"] = dict(precond=hx.HX_PC_PMG, pmg=mg.value)
     ref = None
     for name, o in forms.items():
         print(f"[bench] solve {name}", file=sys.stderr, flush=True)
@@ -131,6 +161,9 @@ def solves(pr, mass_pr, maxit=20000):
                          err_vs_exact=float((xs - u_dev).abs().max() / u_dev.abs().max()),
                          gdofs_per_iteration=round(pr.n * info["iterations"] / max(info["solve_seconds"], 1e-9) / 1e9,
                                                    2))
+    out["fp64_fcg_pmg"].update(degrees=pmg_degrees(pr.p), hierarchy_setup_seconds=round(mg_setup, 3),
+                               opts={k: getattr(hx.hx_pmg_opts_default(), k) for k, _ in hx.hx_pmg_opts._fields_})
+    pmg_close(mg, coarse)
     return out
 
 
@@ -183,6 +216,7 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     """Scalar variable-coefficient diffusion, p=6, q=8: FP64 PCG vs FP32/bf16-matrix-core Chebyshev forms."""
     from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd import learned
+    from paper_2109_04996_amd.inputs import kappa_field_params
     print(f"[bench] kappa Chebyshev suite p={p} N={N}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     pr, b = learned.problem_with_kappa(N, p, p + 2, "gauss", kappa_seed)
@@ -205,6 +239,10 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     _, out["ir_fp32op_cheb4_bf16split"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
                                                        cheb_prec=hx.HX_BF16_SPLIT, inner_qdata=hx.HX_FP32,
                                                        flexible=1)
+    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512))
+    _, out["fp64_fcg_pmg"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+    out["fp64_fcg_pmg"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+    pmg_close(mg, coarse)
     pr.close()
     return out
 

@@ -229,7 +229,10 @@ void hx_op_destroy(hx_op op);
 /* Solves                                                                    */
 /* ------------------------------------------------------------------------ */
 
-enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2, HX_PC_MLP = 3 };
+enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2, HX_PC_MLP = 3, HX_PC_PMG = 4 };
+
+/* p-multigrid hierarchy (declared below) */
+typedef struct hx_pmg_s *hx_pmg;
 enum { HX_SOLVE_FP64 = 0, HX_SOLVE_IR = 1 };
 
 typedef struct {
@@ -274,6 +277,8 @@ typedef struct {
                           Used when the operator needs no zero-fill of its output
                           and the preconditioner is not HX_PC_MLP. 0: launch every
                           kernel on the caller's stream                         */
+  hx_pmg pmg;          /* HX_PC_PMG: the hierarchy, whose finest operator is the
+                          solved one; one V-cycle per iteration, flexible CG    */
 } hx_solve_opts;
 
 typedef struct {
@@ -296,7 +301,7 @@ typedef struct {
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
  * inner_rtol 1e-4, inner_maxit 10000, FP64 inner qdata, flexible 0, no network,
  * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1,
- * graph 0. */
+ * graph 0, no hierarchy. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:
@@ -377,6 +382,56 @@ hx_status hx_mlp_train(hx_mlp net, const float *X, const float *T, int64_t nsamp
 hx_status hx_op_mlp_features(hx_op op, const double *r, float *X, float *rnorm, hx_stream s);
 hx_status hx_op_mlp_targets(hx_op op, const double *err, const float *rnorm, float *T, hx_stream s);
 hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, const double *r, double *z, hx_stream s);
+
+/* ------------------------------------------------------------------------ */
+/* p-multigrid                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* A V-cycle over polynomial degrees on one mesh (the preconditioning section:
+ * multigrid over a hierarchy of degrees with matrix-free smoothers). Level 0 is
+ * the finest. P_l, the prolongation from level l+1 to level l, evaluates a
+ * coarse function (its values at the coarse GLL nodes of each element) at the
+ * fine GLL nodes: a fine node shared by several elements takes its value from
+ * one of them (all give the same value up to rounding). The restriction is P_l^T.
+ * One V-cycle z = V_0 r:
+ *   level l < L-1: z = S_l r (Chebyshev smoothing from 0: smooth_degree steps on
+ *     D_l^-1 A_l over [lam_hi / smooth_ratio, lam_hi], lam_hi = 1.1 lam_max(D_l^-1 A_l));
+ *     z += P_l V_{l+1}(P_l^T (r - A_l z)); z += S_l (r - A_l z);
+ *   level L-1: Jacobi-PCG from 0 on A_{L-1} e = r.
+ * Residuals, corrections and results are zero at constrained nodes. */
+typedef struct {
+  int smooth_degree;   /* Chebyshev steps per smoothing (>= 1)                 */
+  double smooth_ratio; /* > 1                                                  */
+  int lanczos_steps;   /* steps of each level's lam_max estimate (>= 2)       */
+  int coarse_maxit;    /* Jacobi-PCG iteration cap on the coarsest level (>= 1) */
+  double coarse_rtol;  /* coarse PCG tolerance relative to its right-hand side;
+                          0: exactly coarse_maxit iterations (a fixed map)       */
+} hx_pmg_opts;
+
+/* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 50,
+ * coarse_rtol 1e-2. */
+void hx_pmg_opts_default(hx_pmg_opts *opts);
+
+/* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):
+ * 2 <= nlevels <= 8, every operator scalar (ncomp 1) and of one kind, degrees
+ * strictly decreasing, meshes with the same elements in the same caller order and
+ * the same corner positions (element e of every level is the same hexahedron in
+ * the same local orientation), every node in some element. Computes each level's
+ * diagonal and lam_max on s and returns after they are done. Errors: HX_EINVAL
+ * (arguments, mismatched levels), HX_EUNSUPPORTED (vector operators), HX_ENOMEM,
+ * HX_EHIP, HX_EBREAKDOWN (a lam_max estimate failed). */
+hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream s, hx_pmg *out);
+int hx_pmg_levels(hx_pmg mg);
+/* lam_max of D_l^-1 A_l as estimated at creation (0 for the coarsest level). */
+hx_status hx_pmg_lambda_max(hx_pmg mg, int level, double *lam_max);
+/* z = V_0 r (device FP64 L-vectors of level 0; z must not alias r). Synchronises s
+ * once per coarse solve (its convergence checks). */
+hx_status hx_pmg_vcycle(hx_pmg mg, const double *r, double *z, hx_stream s);
+/* y_l = P_l x_{l+1} and y_{l+1} = P_l^T r_l, 0 <= level < nlevels-1 (device FP64
+ * L-vectors of the two levels; no masking). Asynchronous. */
+hx_status hx_pmg_prolong(hx_pmg mg, int level, const double *x_coarse, double *y_fine, hx_stream s);
+hx_status hx_pmg_restrict(hx_pmg mg, int level, const double *r_fine, double *y_coarse, hx_stream s);
+void hx_pmg_destroy(hx_pmg mg);
 
 /* Checkpoint: 8-byte magic "HXMLP1", int32 n_in, n_hidden, n_out, 0, then the FP32
  * parameters in the layout above. */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -156,6 +157,34 @@ struct hx_op_s {
   hx::DevBuf<uint16_t> qdata_bf16;
 };
 
+// p-multigrid hierarchy: level 0 finest. Level l (l < L-1) also holds the transfer to level l+1.
+struct hx_pmg_s {
+  struct Level {
+    hx_op op = nullptr;
+    int64_t n = 0;
+    double lam_max = 0.0;
+    hx::DevBuf<double> work;  // 10 n: the level's vectors
+    hx::DevBuf<double> red;   // reduction partials and device scalars of its solves
+    // transfer from level l+1 (coarse) to this level (fine); empty on the coarsest level
+    int Pc = 0;
+    hx::DevBuf<double> interp;     // [Pf][Pc]: coarse Lagrange basis at the fine GLL nodes
+    hx::DevBuf<int32_t> cmap;      // [E] fine internal position -> coarse internal position
+    hx::DevBuf<int32_t> owner;     // [n] the fine internal element that writes the node in a prolongation
+    hx::DevBuf<double> ecoarse;    // [E][Pc^3] coarse E-vector of a restriction (coarse internal order)
+    hx::DevBuf<int64_t> csr_ptr;   // [n_coarse + 1]
+    hx::DevBuf<int32_t> csr_slot;  // E-vector slots of each coarse node, ascending
+  };
+  hx_pmg_s() = default;
+  hx_pmg_s(const hx_pmg_s &) = delete;
+  hx_pmg_s &operator=(const hx_pmg_s &) = delete;
+  ~hx_pmg_s() {
+    if (hS) (void)hipHostFree(hS);
+  }
+  hx_pmg_opts opts{};
+  std::vector<std::unique_ptr<Level>> lv;
+  double *hS = nullptr;  // pinned host scalars of the coarse solve
+};
+
 namespace hx {
 
 // ---------------------------------------------------------------- kernels (launchers)
@@ -179,5 +208,10 @@ hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyA
 hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s, int *bad_det);
 hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
 hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s);
+// p-multigrid transfer between level l (fine) and l+1; fm: free mask applied to the output, or null
+hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf, const uint8_t *fm, hipStream_t s);
+hx_status launch_restrict(const hx_pmg_s &mg, int l, const double *rf, double *yc, const uint8_t *fm, hipStream_t s);
+// each level's diagonal and lam_max (solver side)
+hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s);
 
 }  // namespace hx

@@ -642,8 +642,103 @@ struct PinnedHost {
   }
 };
 
+// ---------------------------------------------------------------- p-multigrid V-cycle
+
+Ctx level_ctx(hx_pmg_s &mg, hx_pmg_s::Level &L, hipStream_t s) {
+  double *red = L.red.ptr;
+  return Ctx{*L.op, s, L.n, 1, red, red + kVecBlocks, red + 3 * kVecBlocks, red + 2 * kVecBlocks, mg.hS, 0};
+}
+
+// z = V_l r. Level l's vectors: r and z are the caller's at level 0 and v.r, v.x below it; the level
+// itself uses v.w, v.p, v.cd, v.ct and v.dinv. The coarsest level runs Jacobi-PCG from 0.
+hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStream_t s) {
+  auto &L = *mg.lv[l];
+  Ctx c = level_ctx(mg, L, s);
+  Vecs<double> v;
+  if (hx_status st = carve(L.work, L.n, v)) return st;
+  const int64_t n = L.n;
+  if (l + 1 == mg.lv.size()) {
+    if (r != v.r) HX_HIP(hipMemcpyAsync(v.r, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double rr0 = 1.0, stop2 = 0.0;
+    int check = mg.opts.coarse_maxit;
+    if (mg.opts.coarse_rtol > 0.0) {
+      HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, s));
+      LAUNCH_V((k_dot<double>), n, v.r, v.r, c.part0);
+      FINAL(c.part0, (const double *)nullptr, FIN_SUM, S_TMP);
+      if (hx_status st = read_scalars(c)) return st;
+      rr0 = c.hS[S_TMP];
+      stop2 = mg.opts.coarse_rtol * mg.opts.coarse_rtol * rr0;
+      check = std::min(10, mg.opts.coarse_maxit);
+    }
+    int it = 0;
+    double rr = 0.0;
+    hx_status st = rr0 > 0.0 ? pcg_core<double>(c, v, nullptr, HX_FP64, rr0, stop2, mg.opts.coarse_maxit, check,
+                                                false, &it, &rr)
+                             : (hipMemsetAsync(v.x, 0, sizeof(double) * n, s) == hipSuccess ? HX_OK : HX_EHIP);
+    if (st == HX_EBREAKDOWN) st = HX_OK;  // keep the iterate reached (a residual that vanished exactly)
+    if (st) return st;
+    if (z != v.x) HX_HIP(hipMemcpyAsync(z, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    return HX_OK;
+  }
+  const uint8_t *fm = L.op->mesh->freemask.ptr;
+  Cheb ch;
+  ch.degree = mg.opts.smooth_degree;
+  ch.lam_hi = 1.1 * L.lam_max;
+  ch.lam_lo = ch.lam_hi / mg.opts.smooth_ratio;
+  auto &C = *mg.lv[l + 1];
+  Vecs<double> vc;
+  if (hx_status st = carve(C.work, C.n, vc)) return st;
+  // pre-smoothing from 0, then the masked residual
+  if (hx_status st = cheb_apply<double>(c, ch, v, r, z, HX_FP64)) return st;
+  if (hx_status st = apply_T(c, z, v.w, HX_FP64)) return st;
+  LAUNCH_V(k_mresid, n, r, fm, v.w);
+  // coarse correction
+  if (hx_status st = launch_restrict(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s)) return st;
+  if (hx_status st = pmg_level(mg, l + 1, vc.r, vc.x, s)) return st;
+  if (hx_status st = launch_prolong(mg, (int)l, vc.x, v.w, fm, s)) return st;
+  LAUNCH_V((k_axpy<double>), n, 1.0, v.w, z);
+  // post-smoothing on the new residual
+  if (hx_status st = apply_T(c, z, v.w, HX_FP64)) return st;
+  LAUNCH_V(k_mresid, n, r, fm, v.w);
+  if (hx_status st = cheb_apply<double>(c, ch, v, v.w, v.p, HX_FP64)) return st;
+  LAUNCH_V((k_axpy<double>), n, 1.0, v.p, z);
+  HX_HIP(hipGetLastError());
+  return HX_OK;
+}
+
 }  // namespace
+
+// each level's work vectors, D^-1 and (above the coarsest) lam_max of D^-1 A by Lanczos
+hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
+  if (!mg.hS) HX_HIP(hipHostMalloc(reinterpret_cast<void **>(&mg.hS), sizeof(double) * S_NSCAL));
+  for (size_t l = 0; l < mg.lv.size(); ++l) {
+    auto &L = *mg.lv[l];
+    hx_op_s &op = *L.op;
+    HX_HIP(L.red.alloc(3 * kVecBlocks + S_NSCAL));
+    Vecs<double> v;
+    if (hx_status st = carve(L.work, L.n, v)) return st;
+    if (!op.diag_valid) {
+      if (op.diag.count < (size_t)L.n) HX_HIP(op.diag.alloc(L.n));
+      if (hx_status st = hx_op_diagonal(&op, op.diag.ptr, s)) return st;
+      op.diag_valid = true;
+    }
+    Ctx c = level_ctx(mg, L, s);
+    LAUNCH_V((k_dinv<double, 1>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
+    HX_HIP(hipGetLastError());
+    if (l + 1 < mg.lv.size())
+      if (hx_status st = lanczos_lambda_max(c, v, mg.opts.lanczos_steps, &L.lam_max)) return st;
+  }
+  HX_HIP(hipStreamSynchronize(s));
+  return HX_OK;
+}
+
 }  // namespace hx
+
+extern "C" hx_status hx_pmg_vcycle(hx_pmg mg, const double *r, double *z, hx_stream s) {
+  if (!mg || !r || !z) return hx::fail(HX_EINVAL, "null argument");
+  if (r == z) return hx::fail(HX_EINVAL, "z must not alias r");
+  return hx::pmg_level(*mg, 0, r, z, static_cast<hipStream_t>(s));
+}
 
 using namespace hx;
 
@@ -669,6 +764,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->stall_factor = 0.1;
   o->mlp_mode = 1;
   o->graph = 0;
+  o->pmg = nullptr;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -676,7 +772,11 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   if (!op || !b || !x || !opts || !info) return fail(HX_EINVAL, "null argument");
   const hx_solve_opts &o = *opts;
   if (o.mode != HX_SOLVE_FP64 && o.mode != HX_SOLVE_IR) return fail(HX_EINVAL, "mode must be HX_SOLVE_FP64 or HX_SOLVE_IR");
-  if (o.precond < HX_PC_NONE || o.precond > HX_PC_MLP) return fail(HX_EINVAL, "precond out of range");
+  if (o.precond < HX_PC_NONE || o.precond > HX_PC_PMG) return fail(HX_EINVAL, "precond out of range");
+  const bool pmg = o.precond == HX_PC_PMG;
+  if (pmg && !o.pmg) return fail(HX_EINVAL, "HX_PC_PMG needs opts.pmg");
+  if (pmg && o.pmg->lv[0]->op != op) return fail(HX_EINVAL, "the hierarchy's finest operator is not the solved one");
+  if (pmg && o.mode != HX_SOLVE_FP64) return fail(HX_EUNSUPPORTED, "HX_PC_PMG runs in HX_SOLVE_FP64 mode");
   if (!(o.rtol > 0) || o.maxit < 1 || o.check_every < 1) return fail(HX_EINVAL, "need rtol > 0, maxit >= 1, check_every >= 1");
   const bool mlp = o.precond == HX_PC_MLP;
   if (mlp && !o.mlp) return fail(HX_EINVAL, "HX_PC_MLP needs opts.mlp");
@@ -709,7 +809,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   hipStream_t s = static_cast<hipStream_t>(stream);
   // graph replay needs a stream that can be captured: the solve then runs on the operator's own
   // stream, after the caller's queued work; it is synchronous, so it has finished on return
-  const bool use_graph = o.graph != 0 && !mlp && op->mesh->nuntouched == 0;
+  const bool use_graph = o.graph != 0 && !mlp && !pmg && op->mesh->nuntouched == 0;
   StreamSync solve_done;
   if (use_graph) {
     if (!op->solve_stream) HX_HIP(hipStreamCreateWithFlags(&op->solve_stream, hipStreamNonBlocking));
@@ -837,13 +937,15 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       if (o.mlp_mode == 1) return mlp_base(r, z);
       return cheb_apply_base(c, chm, v, mlp_base, r, z);
     };
+    PrecFn<double> pcp = [&](const double *r, double *z) -> hx_status { return pmg_level(*o.pmg, 0, r, z, s); };
     const PrecFn<double> *pc_cheb = cheb ? ((o.cheb_prec == HX_FP64) ? &pc64 : &pc32) : nullptr;
-    const PrecFn<double> *pc = mlp ? &pcm : pc_cheb;
+    const PrecFn<double> *pc = mlp ? &pcm : pmg ? &pcp : pc_cheb;
     const double stop2 = o.rtol * o.rtol * bb;
     int it = 0;
     double rre = 0;
-    // the learned preconditioner is nonlinear in r: flexible CG, with a stall check for the fallback
-    result = pcg_core<double>(c, v, pc, HX_FP64, rr, stop2, o.maxit, o.check_every, o.flexible != 0 || mlp, &it,
+    // the learned preconditioner and the V-cycle (its coarse PCG) are nonlinear in r: flexible CG,
+    // with a stall check for the learned one's fallback
+    result = pcg_core<double>(c, v, pc, HX_FP64, rr, stop2, o.maxit, o.check_every, o.flexible != 0 || mlp || pmg, &it,
                               &rre, mlp ? o.stall_window : 0, o.stall_factor);
     if (mlp) HX_HIP(hipMemcpyAsync(v.cd, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));  // x before the learned phase
     LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);

@@ -20,7 +20,7 @@ HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOW
 HX_GAUSS, HX_GLL = 0, 1
 HX_MASS, HX_DIFFUSION = 0, 1
 HX_FP64, HX_FP32, HX_BF16, HX_BF16_SPLIT = 0, 1, 2, 3
-HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP = 0, 1, 2, 3
+HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP, HX_PC_PMG = 0, 1, 2, 3, 4
 HX_SOLVE_FP64, HX_SOLVE_IR = 0, 1
 
 STATUS_NAMES = {0: "HX_OK", -1: "HX_EINVAL", -2: "HX_ERANGE", -3: "HX_EUNSUPPORTED", -4: "HX_EGEOM",
@@ -56,7 +56,12 @@ class hx_solve_opts(C.Structure):
                 ("cheb_ratio", C.c_double), ("cheb_prec", C.c_int), ("lanczos_steps", C.c_int),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
                 ("flexible", C.c_int), ("mlp", C.c_void_p), ("fallback", C.c_int), ("stall_window", C.c_int),
-                ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int)]
+                ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int), ("pmg", C.c_void_p)]
+
+
+class hx_pmg_opts(C.Structure):
+    _fields_ = [("smooth_degree", C.c_int), ("smooth_ratio", C.c_double), ("lanczos_steps", C.c_int),
+                ("coarse_maxit", C.c_int), ("coarse_rtol", C.c_double)]
 
 
 class hx_train_opts(C.Structure):
@@ -114,6 +119,14 @@ SIGNATURES = [
     ("hx_op_mlp_targets", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hx_op_mlp_precond", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hx_pcg_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(hx_solve_opts), C.POINTER(hx_solve_info), _VP]),
+    ("hx_pmg_opts_default", None, [C.POINTER(hx_pmg_opts)]),
+    ("hx_pmg_create", C.c_int, [_VP, C.c_int, C.POINTER(hx_pmg_opts), _VP, C.POINTER(_VP)]),
+    ("hx_pmg_levels", C.c_int, [_VP]),
+    ("hx_pmg_lambda_max", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double)]),
+    ("hx_pmg_vcycle", C.c_int, [_VP, _VP, _VP, _VP]),
+    ("hx_pmg_prolong", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
+    ("hx_pmg_restrict", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
+    ("hx_pmg_destroy", None, [_VP]),
 ]
 
 _lib = None
@@ -291,6 +304,51 @@ def hx_pcg_solve(op, b, x, opts: hx_solve_opts, stream=None, raise_on_error=True
     if raise_on_error and code != HX_OK:
         raise HexpaError(code, "hx_pcg_solve", hx_last_error())
     return d
+
+
+# ---------------------------------------------------------------------------- p-multigrid
+
+def hx_pmg_opts_default(**overrides) -> hx_pmg_opts:
+    o = hx_pmg_opts()
+    load().hx_pmg_opts_default(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def hx_pmg_create(ops, opts: hx_pmg_opts, stream=None):
+    arr = (C.c_void_p * len(ops))(*[o.value if isinstance(o, C.c_void_p) else o for o in ops])
+    h = C.c_void_p()
+    _check(load().hx_pmg_create(arr, len(ops), C.byref(opts), _stream(stream), C.byref(h)), "hx_pmg_create")
+    return h
+
+
+def hx_pmg_levels(mg) -> int:
+    return load().hx_pmg_levels(mg)
+
+
+def hx_pmg_lambda_max(mg, level) -> float:
+    v = C.c_double()
+    _check(load().hx_pmg_lambda_max(mg, level, C.byref(v)), "hx_pmg_lambda_max")
+    return v.value
+
+
+def hx_pmg_vcycle(mg, r, z, stream=None):
+    _check(load().hx_pmg_vcycle(mg, _ptr(r), _ptr(z), _stream(stream)), "hx_pmg_vcycle")
+
+
+def hx_pmg_prolong(mg, level, x_coarse, y_fine, stream=None):
+    _check(load().hx_pmg_prolong(mg, level, _ptr(x_coarse), _ptr(y_fine), _stream(stream)), "hx_pmg_prolong")
+
+
+def hx_pmg_restrict(mg, level, r_fine, y_coarse, stream=None):
+    _check(load().hx_pmg_restrict(mg, level, _ptr(r_fine), _ptr(y_coarse), _stream(stream)), "hx_pmg_restrict")
+
+
+def hx_pmg_destroy(mg):
+    load().hx_pmg_destroy(mg)
 
 
 # ---------------------------------------------------------------------------- network

@@ -95,3 +95,66 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class Hierarchy:
+    """p-multigrid over polynomial degrees on one lattice mesh.
+
+    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, **pmg_opts)``:
+    level l is a ``Problem`` of degree ``degrees[l]`` (strictly decreasing) with
+    q = p + 1 GLL points or q = p + 2 Gauss points, on the same elements (same
+    shuffle); ``meshes`` overrides the lattice meshes level by level.
+    """
+
+    def __init__(self, N: int, degrees, rule: str = "gll", kind: str = "diffusion", warp="A", shuffle_seed=0,
+                 kappa: dict | None = None, meshes=None, **pmg_opts):
+        self.levels = []
+        for l, p in enumerate(degrees):
+            q = p + 1 if rule == "gll" else p + 2
+            self.levels.append(Problem(N, p, q, rule, kind, warp=warp, shuffle_seed=shuffle_seed, kappa=kappa,
+                                       mesh=None if meshes is None else meshes[l]))
+        self.h = hx.hx_pmg_create([pr.h_op for pr in self.levels], hx.hx_pmg_opts_default(**pmg_opts))
+
+    @property
+    def fine(self) -> Problem:
+        return self.levels[0]
+
+    def lambda_max(self, level: int) -> float:
+        return hx.hx_pmg_lambda_max(self.h, level)
+
+    def vcycle(self, r, z=None):
+        z = self.fine.zeros() if z is None else z
+        hx.hx_pmg_vcycle(self.h, r, z)
+        return z
+
+    def prolong(self, level: int, x_coarse):
+        y = self.levels[level].zeros()
+        hx.hx_pmg_prolong(self.h, level, x_coarse, y)
+        return y
+
+    def restrict(self, level: int, r_fine):
+        y = self.levels[level + 1].zeros()
+        hx.hx_pmg_restrict(self.h, level, r_fine, y)
+        return y
+
+    def solve(self, b, x=None, raise_on_error=True, **opts):
+        return self.fine.solve(b, x, raise_on_error=raise_on_error, precond=hx.HX_PC_PMG, pmg=self.h.value, **opts)
+
+    def close(self):
+        if getattr(self, "h", None):
+            hx.hx_pmg_destroy(self.h)
+            self.h = None
+        for pr in getattr(self, "levels", []):
+            pr.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
