@@ -146,7 +146,9 @@ def solves(pr, mass_pr, maxit=20000):
         x = pr.zeros()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = pr.solve(b, x=x, rtol=1e-8, maxit=maxit, check_every=25, raise_on_error=False, **o)
+        # a V-cycle costs several applies: check every iteration
+        x, info = pr.solve(b, x=x, rtol=1e-8, maxit=maxit, check_every=1 if "pmg" in o else 25,
+                           raise_on_error=False, **o)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         xs = x.double()
@@ -171,8 +173,8 @@ def _timed_solve(pr, b, ref=None, **o):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x, info = pr.solve(b, rtol=o.pop("rtol", 1e-8), maxit=o.pop("maxit", 40000), check_every=25,
-                       raise_on_error=False, **o)
+    x, info = pr.solve(b, rtol=o.pop("rtol", 1e-8), maxit=o.pop("maxit", 40000),
+                       check_every=1 if "pmg" in o else 25, raise_on_error=False, **o)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rec = dict(status=info["status"], iterations=info["iterations"], outer=info["outer_iterations"],
@@ -261,6 +263,12 @@ def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 100
           file=sys.stderr, flush=True)
     pr, b = learned.problem_with_kappa(N_eval, p, p + 2, "gauss", eval_seed)
     res = learned.compare_solves(pr, b, net)
+    # the stronger non-learned baseline: p-multigrid (degrees p, p/2, ..., 1) in flexible CG
+    from paper_2109_04996_amd.inputs import kappa_field_params
+    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(eval_seed, M=512))
+    _, res["pmg"] = _timed_solve(pr, b, None, precond=hx.HX_PC_PMG, pmg=mg.value)
+    res["pmg"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+    pmg_close(mg, coarse)
     out = dict(workload=f"diffusion with kappa (held-out seed {eval_seed}), p={p}, q={p + 2} Gauss, mesh A "
                         f"{N_eval}^3, {pr.mesh['nnodes']} DOFs, b = B 1, rtol 1e-8",
                training=dict(rows=int(X.shape[0]), data_seconds=round(t_data, 2),
@@ -273,9 +281,10 @@ def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 100
     # each learned form against its own fallback, and against plain FP64 Jacobi PCG
     out["gain"] = dict(learned_vs_jacobi=round(t["jacobi"] / max(t["learned"], 1e-9), 3),
                        learned_cheb4_vs_chebyshev4=round(t["chebyshev4"] / max(t["learned_cheb4"], 1e-9), 3),
-                       learned_cheb4_vs_jacobi=round(t["jacobi"] / max(t["learned_cheb4"], 1e-9), 3))
+                       learned_cheb4_vs_jacobi=round(t["jacobi"] / max(t["learned_cheb4"], 1e-9), 3),
+                       best_learned_vs_pmg=round(t["pmg"] / max(min(t["learned"], t["learned_cheb4"]), 1e-9), 3))
     best_learned = min(t["learned"], t["learned_cheb4"])
-    best_plain = min(t["jacobi"], t["chebyshev4"], t["chebyshev4_fp32"])
+    best_plain = min(t["jacobi"], t["chebyshev4"], t["chebyshev4_fp32"], t["pmg"])
     saved = best_plain - best_learned
     out["break_even_solves"] = (round((t_data + info["seconds"]) / saved, 1) if saved > 0 else None)
     pr.close()
@@ -434,6 +443,8 @@ def main():
     ap.add_argument("--pmc-kernels", action="store_true",
                     help="short run for the FLOP-rate counter pass: 4 applies of each hot kernel (BP5 p=7 FP64 and "
                          "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
+    ap.add_argument("--pmg-vcycles", type=int, default=0,
+                    help="time this many p-multigrid V-cycles (degrees p, p/2, ..., 1) on the BP5 problem and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the library implements the single-GPU "
@@ -487,6 +498,25 @@ def main():
         print(json.dumps(dict(pmc_kernels=True, workloads=["bp5_p7_n48 FP64 and FP32",
                                                            "p6_q8_gauss_n48 FP64, FP32, bf16, bf16 split"])),
               flush=True)
+        return
+    if a.pmg_vcycles:
+        mg, coarse, mg_setup = pmg_hierarchy(pr, "gll")
+        r = pr.to_dev(uniform_vector(n, 2) * (mesh["boundary"] == 0))
+        z = pr.zeros()
+        for _ in range(2):
+            hx.hx_pmg_vcycle(mg, r, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.pmg_vcycles):
+            hx.hx_pmg_vcycle(mg, r, z)
+        torch.cuda.synchronize()
+        ms_vc = 1e3 * (time.perf_counter() - t0) / a.pmg_vcycles
+        print(json.dumps(dict(pmg_vcycles=a.pmg_vcycles, ms_per_vcycle=round(ms_vc, 3), degrees=pmg_degrees(p),
+                              setup_seconds=round(mg_setup, 3), workload=f"bp5_p{p}_n{N}",
+                              opts={k: getattr(hx.hx_pmg_opts_default(), k) for k, _ in hx.hx_pmg_opts._fields_})),
+              flush=True)
+        pmg_close(mg, coarse)
+        pr.close()
         return
     if a.pmc_run:
         # reference copy of known size (1 GiB read + 1 GiB written) for scaling the counters

@@ -284,7 +284,9 @@ typedef struct {
 typedef struct {
   int iterations;        /* PCG iterations (sum of inner iterations for IR)  */
   int outer_iterations;  /* IR refinement steps (0 for FP64 PCG)             */
-  int operator_applies;  /* applies of A in any precision                    */
+  int operator_applies;  /* applies of A in any precision (HX_PC_PMG: with the
+                            V-cycles' applies of this operator, not those of
+                            the coarser levels)                               */
   double rel_residual;   /* recurrence residual at exit                      */
   double true_rel_residual; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
   double lam_max;        /* Chebyshev: estimated lambda_max of D^-1 A (of M A
@@ -408,8 +410,8 @@ typedef struct {
                           0: exactly coarse_maxit iterations (a fixed map)       */
 } hx_pmg_opts;
 
-/* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 50,
- * coarse_rtol 1e-2. */
+/* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 30,
+ * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations). */
 void hx_pmg_opts_default(hx_pmg_opts *opts);
 
 /* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):

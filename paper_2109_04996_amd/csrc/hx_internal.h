@@ -163,13 +163,13 @@ struct hx_pmg_s {
     hx_op op = nullptr;
     int64_t n = 0;
     double lam_max = 0.0;
+    int64_t applies = 0;      // operator applies made by V-cycles on this level
     hx::DevBuf<double> work;  // 10 n: the level's vectors
     hx::DevBuf<double> red;   // reduction partials and device scalars of its solves
     // transfer from level l+1 (coarse) to this level (fine); empty on the coarsest level
     int Pc = 0;
     hx::DevBuf<double> interp;     // [Pf][Pc]: coarse Lagrange basis at the fine GLL nodes
     hx::DevBuf<int32_t> cmap;      // [E] fine internal position -> coarse internal position
-    hx::DevBuf<int32_t> owner;     // [n] the fine internal element that writes the node in a prolongation
     hx::DevBuf<double> ecoarse;    // [E][Pc^3] coarse E-vector of a restriction (coarse internal order)
     hx::DevBuf<int64_t> csr_ptr;   // [n_coarse + 1]
     hx::DevBuf<int32_t> csr_slot;  // E-vector slots of each coarse node, ascending

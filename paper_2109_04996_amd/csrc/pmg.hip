@@ -3,7 +3,8 @@
 //
 // Prolongation y_f = P x_c: each element interpolates the coarse values at its coarse GLL nodes to
 // its fine GLL nodes by three 1D contractions (the coarse Lagrange basis evaluated at the fine
-// nodes, Pf x Pc), and writes only the fine nodes it owns, so each node is written exactly once
+// nodes, Pf x Pc), and writes only the fine nodes it owns (the fine mesh's ownership bits: the
+// first element in internal order that holds the node), so each node is written exactly once
 // (no scatter). Restriction y_c = P^T r_f: each element applies the transposed contractions to the
 // fine values it owns (zero elsewhere) and stores a coarse E-vector; a second kernel sums every
 // coarse node's E-vector slots in ascending slot order (deterministic, no atomics).
@@ -24,10 +25,24 @@ namespace {
 constexpr int kTW = 4;            // wavefronts (elements) per workgroup
 constexpr int kTBuf = kMaxP * kMaxP * kMaxP;
 
+// fine node of local (line ji = i + Pf j, layer k): from the affine numbering {base, s_j, s_k}, or the index
+template <bool AFF>
+__device__ __forceinline__ int32_t fine_node(const int32_t *__restrict__ idx_f, const int32_t *__restrict__ aff,
+                                             int64_t e, int Pf, int ji, int k) {
+  if constexpr (AFF) {
+    const int i = ji % Pf, j = ji / Pf;
+    return aff[e * 4] + i + j * aff[e * 4 + 1] + k * aff[e * 4 + 2];
+  } else {
+    return idx_f[e * Pf * Pf * Pf + k * Pf * Pf + ji];
+  }
+}
+
+template <bool AFF>
 __global__ void __launch_bounds__(kTW * 64)
 k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
-          const int32_t *__restrict__ idx_c, const int32_t *__restrict__ owner, const double *__restrict__ I,
-          const uint8_t *__restrict__ fm, const double *__restrict__ xc, double *__restrict__ yf) {
+          const int32_t *__restrict__ aff, const int32_t *__restrict__ idx_c, const uint16_t *__restrict__ own,
+          const double *__restrict__ I, const uint8_t *__restrict__ fm, const double *__restrict__ xc,
+          double *__restrict__ yf) {
   __shared__ double sA[kTW][kTBuf], sB[kTW][kTBuf];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -60,15 +75,18 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
       const int ji = t % Pf2, k = t / Pf2;
       double v = 0.0;
       for (int c = 0; c < Pc; ++c) v += I[k * Pc + c] * A[c * Pf2 + ji];
-      const int32_t node = idx_f[e * Pf3 + t];
-      if (owner[node] == (int32_t)e) yf[node] = (fm && !fm[node]) ? 0.0 : v;
+      if ((own[e * Pf2 + ji] >> k) & 1) {
+        const int32_t node = fine_node<AFF>(idx_f, aff, e, Pf, ji, k);
+        yf[node] = (fm && !fm[node]) ? 0.0 : v;
+      }
     }
 }
 
+template <bool AFF>
 __global__ void __launch_bounds__(kTW * 64)
 k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
-                const int32_t *__restrict__ owner, const double *__restrict__ I, const double *__restrict__ rf,
-                double *__restrict__ ec_out) {
+                const int32_t *__restrict__ aff, const uint16_t *__restrict__ own, const double *__restrict__ I,
+                const double *__restrict__ rf, double *__restrict__ ec_out) {
   __shared__ double sA[kTW][kTBuf], sB[kTW][kTBuf];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -77,8 +95,8 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
   const int Pc2 = Pc * Pc, Pc3 = Pc2 * Pc, Pf2 = Pf * Pf, Pf3 = Pf2 * Pf;
   if (live)
     for (int t = l; t < Pf3; t += 64) {
-      const int32_t node = idx_f[e * Pf3 + t];
-      A[t] = owner[node] == (int32_t)e ? rf[node] : 0.0;
+      const int ji = t % Pf2, k = t / Pf2;
+      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? rf[fine_node<AFF>(idx_f, aff, e, Pf, ji, k)] : 0.0;
     }
   __syncthreads();
   if (live)  // r3: B[c][j][i] = sum_k I[k][c] A[k][j][i]   (c < Pc; j, i < Pf)
@@ -126,8 +144,13 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem == 0) return HX_OK;
-  hipLaunchKernelGGL(k_prolong, dim3((unsigned)blocks_for(mf->nelem)), dim3(kTW * 64), 0, s, mf->nelem, mf->P, F.Pc,
-                     F.cmap.ptr, mf->idx.ptr, mc->idx.ptr, F.owner.ptr, F.interp.ptr, fm, xc, yf);
+  const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+  if (mf->idx_affine.count)
+    hipLaunchKernelGGL(k_prolong<true>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
+  else
+    hipLaunchKernelGGL(k_prolong<false>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -135,9 +158,15 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf
 hx_status launch_restrict(const hx_pmg_s &mg, int l, const double *rf, double *yc, const uint8_t *fm, hipStream_t s) {
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
-  if (mf->nelem > 0)
-    hipLaunchKernelGGL(k_restrict_elem, dim3((unsigned)blocks_for(mf->nelem)), dim3(kTW * 64), 0, s, mf->nelem, mf->P,
-                       F.Pc, F.cmap.ptr, mf->idx.ptr, F.owner.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
+  if (mf->nelem > 0) {
+    const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+    if (mf->idx_affine.count)
+      hipLaunchKernelGGL(k_restrict_elem<true>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
+    else
+      hipLaunchKernelGGL(k_restrict_elem<false>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
+  }
   const int64_t nc = mc->nnodes;
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nc + 255) / 256, 4096));
   hipLaunchKernelGGL(k_restrict_sum, dim3(nb), dim3(256), 0, s, nc, F.csr_ptr.ptr, F.csr_slot.ptr, F.ecoarse.ptr, fm, yc);
@@ -151,7 +180,7 @@ using namespace hx;
 
 namespace {
 
-// The transfer between fine level l and coarse level l + 1: element map, node owners, the coarse
+// The transfer between fine level l and coarse level l + 1: element map, the coarse
 // node -> E-vector slot lists and the 1D interpolation table.
 hx_status build_transfer(hx_pmg_s::Level &F, const hx_pmg_s::Level &C) {
   const hx_mesh mf = F.op->mesh, mc = C.op->mesh;
@@ -181,13 +210,6 @@ hx_status build_transfer(hx_pmg_s::Level &F, const hx_pmg_s::Level &C) {
           return fail(HX_EINVAL, "p-multigrid levels do not share the element geometry (element " +
                                      std::to_string(mf->order[t]) + ", corner " + std::to_string(c) + ")");
     }
-  // owners: the first fine internal element holding each node
-  std::vector<int32_t> owner(mf->nnodes, -1);
-  for (int64_t t = 0; t < E; ++t)
-    for (int l = 0; l < Pf3; ++l) {
-      const int32_t g = idf[(size_t)t * Pf3 + l];
-      if (owner[g] < 0) owner[g] = (int32_t)t;
-    }
   // coarse node -> E-vector slots (coarse internal order), ascending
   std::vector<int64_t> ptr(mc->nnodes + 1, 0);
   for (int32_t g : idc) ++ptr[g + 1];
@@ -203,7 +225,6 @@ hx_status build_transfer(hx_pmg_s::Level &F, const hx_pmg_s::Level &C) {
   F.Pc = Pc;
   HX_HIP(F.interp.upload(I.data(), I.size()));
   HX_HIP(F.cmap.upload(cmap.data(), cmap.size()));
-  HX_HIP(F.owner.upload(owner.data(), owner.size()));
   HX_HIP(F.csr_ptr.upload(ptr.data(), ptr.size()));
   HX_HIP(F.csr_slot.upload(slot.data(), slot.size()));
   HX_HIP(F.ecoarse.alloc((size_t)E * Pc3));
@@ -217,8 +238,8 @@ extern "C" void hx_pmg_opts_default(hx_pmg_opts *o) {
   o->smooth_degree = 3;
   o->smooth_ratio = 15.0;
   o->lanczos_steps = 20;
-  o->coarse_maxit = 50;
-  o->coarse_rtol = 1e-2;
+  o->coarse_maxit = 30;
+  o->coarse_rtol = 0.1;
 }
 
 extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream stream,

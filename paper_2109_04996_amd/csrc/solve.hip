@@ -676,6 +676,7 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStrea
                                                 false, &it, &rr)
                              : (hipMemsetAsync(v.x, 0, sizeof(double) * n, s) == hipSuccess ? HX_OK : HX_EHIP);
     if (st == HX_EBREAKDOWN) st = HX_OK;  // keep the iterate reached (a residual that vanished exactly)
+    L.applies += c.applies;
     if (st) return st;
     if (z != v.x) HX_HIP(hipMemcpyAsync(z, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     return HX_OK;
@@ -702,6 +703,7 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStrea
   LAUNCH_V(k_mresid, n, r, fm, v.w);
   if (hx_status st = cheb_apply<double>(c, ch, v, v.w, v.p, HX_FP64)) return st;
   LAUNCH_V((k_axpy<double>), n, 1.0, v.p, z);
+  L.applies += c.applies;
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -884,6 +886,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   const auto t0 = std::chrono::steady_clock::now();
   info->setup_seconds = std::chrono::duration<double>(t0 - t_setup0).count();
   c.applies = 0;
+  const int64_t pmg_applies0 = pmg ? o.pmg->lv[0]->applies : 0;
 
   if (o.use_x0) {
     if (NC == 1) LAUNCH_V((k_maskset<1>), n, op->mesh->freemask.ptr, x);
@@ -1011,7 +1014,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   HX_HIP(hipStreamSynchronize(s));
   const auto t1 = std::chrono::steady_clock::now();
   info->solve_seconds = std::chrono::duration<double>(t1 - t0).count();
-  info->operator_applies = c.applies;
+  info->operator_applies = c.applies + (pmg ? (int)(o.pmg->lv[0]->applies - pmg_applies0) : 0);
   double rr_true = 0;
   if (hx_status st = residual(&rr_true)) return st;
   info->true_rel_residual = std::sqrt(rr_true) / bn;
