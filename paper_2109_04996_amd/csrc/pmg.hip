@@ -22,8 +22,13 @@
 namespace hx {
 namespace {
 
-constexpr int kTW = 4;            // wavefronts (elements) per workgroup
-constexpr int kTBuf = kMaxP * kMaxP * kMaxP;
+constexpr int kTW = 4;  // wavefronts (elements) per workgroup
+
+// LDS doubles per element: the two intermediate tensors of each transfer (A, then B)
+__host__ __device__ constexpr int prolong_lds_a(int Pf, int Pc) { return Pc * Pf * Pf > Pc * Pc * Pc ? Pc * Pf * Pf : Pc * Pc * Pc; }
+__host__ __device__ constexpr int prolong_lds_b(int Pf, int Pc) { return Pc * Pc * Pf; }
+__host__ __device__ constexpr int restrict_lds_a(int Pf, int Pc) { return Pf * Pf * Pf; }
+__host__ __device__ constexpr int restrict_lds_b(int Pf, int Pc) { return Pc * Pf * Pf; }
 
 // fine node of local (line ji = i + Pf j, layer k): from the affine numbering {base, s_j, s_k}, or the index
 template <bool AFF>
@@ -43,11 +48,11 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
           const int32_t *__restrict__ aff, const int32_t *__restrict__ idx_c, const uint16_t *__restrict__ own,
           const double *__restrict__ I, const uint8_t *__restrict__ fm, const double *__restrict__ xc,
           double *__restrict__ yf) {
-  __shared__ double sA[kTW][kTBuf], sB[kTW][kTBuf];
+  extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
   const bool live = e < E;
-  double *A = sA[w], *B = sB[w];
+  double *A = smem + w * (prolong_lds_a(Pf, Pc) + prolong_lds_b(Pf, Pc)), *B = A + prolong_lds_a(Pf, Pc);
   const int Pc3 = Pc * Pc * Pc, Pf2 = Pf * Pf, Pf3 = Pf2 * Pf;
   if (live) {
     const int64_t ec = cmap[e];
@@ -87,11 +92,11 @@ __global__ void __launch_bounds__(kTW * 64)
 k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
                 const int32_t *__restrict__ aff, const uint16_t *__restrict__ own, const double *__restrict__ I,
                 const double *__restrict__ rf, double *__restrict__ ec_out) {
-  __shared__ double sA[kTW][kTBuf], sB[kTW][kTBuf];
+  extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
   const bool live = e < E;
-  double *A = sA[w], *B = sB[w];
+  double *A = smem + w * (restrict_lds_a(Pf, Pc) + restrict_lds_b(Pf, Pc)), *B = A + restrict_lds_a(Pf, Pc);
   const int Pc2 = Pc * Pc, Pc3 = Pc2 * Pc, Pf2 = Pf * Pf, Pf3 = Pf2 * Pf;
   if (live)
     for (int t = l; t < Pf3; t += 64) {
@@ -145,11 +150,12 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem == 0) return HX_OK;
   const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+  const size_t lds = sizeof(double) * kTW * (prolong_lds_a(mf->P, F.Pc) + prolong_lds_b(mf->P, F.Pc));
   if (mf->idx_affine.count)
-    hipLaunchKernelGGL(k_prolong<true>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+    hipLaunchKernelGGL(k_prolong<true>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                        mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
   else
-    hipLaunchKernelGGL(k_prolong<false>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+    hipLaunchKernelGGL(k_prolong<false>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                        mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
   HX_HIP(hipGetLastError());
   return HX_OK;
@@ -160,11 +166,12 @@ hx_status launch_restrict(const hx_pmg_s &mg, int l, const double *rf, double *y
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem > 0) {
     const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+    const size_t lds = sizeof(double) * kTW * (restrict_lds_a(mf->P, F.Pc) + restrict_lds_b(mf->P, F.Pc));
     if (mf->idx_affine.count)
-      hipLaunchKernelGGL(k_restrict_elem<true>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+      hipLaunchKernelGGL(k_restrict_elem<true>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                          mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
     else
-      hipLaunchKernelGGL(k_restrict_elem<false>, g, b, 0, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+      hipLaunchKernelGGL(k_restrict_elem<false>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                          mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
   }
   const int64_t nc = mc->nnodes;
