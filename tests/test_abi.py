@@ -72,6 +72,17 @@ def test_null_handles(lib):
     assert lib.hx_op_apply(None, None, None, None) == hx.HX_EINVAL
     assert lib.hx_op_diagonal(None, None, None) == hx.HX_EINVAL
     assert lib.hx_pcg_solve(None, None, None, None, None, None) == hx.HX_EINVAL
+    o = hx.hx_pmg_opts_default()
+    h = C.c_void_p()
+    assert lib.hx_pmg_create(None, 2, C.byref(o), None, C.byref(h)) == hx.HX_EINVAL
+    ops = (C.c_void_p * 2)(None, None)
+    assert lib.hx_pmg_create(ops, 1, C.byref(o), None, C.byref(h)) == hx.HX_EINVAL  # nlevels < 2
+    assert lib.hx_pmg_create(ops, 2, C.byref(o), None, C.byref(h)) == hx.HX_EINVAL  # null operators
+    assert lib.hx_pmg_vcycle(None, None, None, None) == hx.HX_EINVAL
+    assert lib.hx_pmg_prolong(None, 0, None, None, None) == hx.HX_EINVAL
+    assert lib.hx_pmg_restrict(None, 0, None, None, None) == hx.HX_EINVAL
+    assert lib.hx_pmg_levels(None) == 0
+    lib.hx_pmg_destroy(None)
     lib.hx_op_destroy(None)
     lib.hx_mesh_destroy(None)
     lib.hx_basis_destroy(None)
@@ -108,6 +119,14 @@ def test_solve_opts_defaults(lib):
     assert o.rtol == 1e-8 and o.precond == hx.HX_PC_JACOBI and o.cheb_degree == 4
     with pytest.raises(AttributeError):
         hx.hx_solve_opts_default(not_a_field=1)
+
+
+def test_pmg_opts_defaults(lib):
+    o = hx.hx_pmg_opts_default()
+    assert (o.smooth_degree, o.smooth_ratio, o.lanczos_steps, o.coarse_maxit, o.coarse_rtol) == (3, 15.0, 20, 30, 0.1)
+    assert hx.hx_solve_opts_default().pmg is None
+    with pytest.raises(AttributeError):
+        hx.hx_pmg_opts_default(not_a_field=1)
 
 
 def test_product_path_does_not_import_oracle():
