@@ -131,3 +131,15 @@ def test_pmg_rejects_bad_hierarchies():
         with pytest.raises(hx.HexpaError, match="level out of range"):
             hx.hx_pmg_prolong(H.h, 1, b, b)
         assert hx.hx_pmg_levels(H.h) == 2
+
+
+def test_pmg_solve_variable_coefficient():
+    """Diffusion with the seeded kappa field (contrast ~1e2) on every level, Gauss q = p + 2."""
+    from paper_2109_04996_amd.inputs import kappa_field_params
+    print("\n[case] pmg solve kappa seed 100 N=8 degrees=(6, 3, 1) gauss", flush=True)
+    with Hierarchy(8, (6, 3, 1), rule="gauss", kappa=kappa_field_params(100, M=512)) as H:
+        b = H.fine.to_dev(uniform_vector(H.fine.n, 2) * (H.fine.mesh["boundary"] == 0))
+        x, info = H.solve(b, rtol=1e-8, check_every=1)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        _, info_j = H.fine.solve(b, rtol=1e-8, check_every=1)
+        assert info["iterations"] * 3 < info_j["iterations"], (info["iterations"], info_j["iterations"])
