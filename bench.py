@@ -140,6 +140,9 @@ def solves(pr, mass_pr, maxit=20000):
     # p-multigrid V-cycle (degrees p, p/2, ..., 1) inside flexible CG
     mg, coarse, mg_setup = pmg_hierarchy(pr, "gll")
     forms["fp64_fcg_pmg"] = dict(precond=hx.HX_PC_PMG, pmg=mg.value)
+    # the same V-cycle in FP32 (vectors, operators with FP32 geometric factors, smoothers) in the FP64 FCG
+    mg32, coarse32, mg32_setup = pmg_hierarchy(pr, "gll", prec=hx.HX_FP32)
+    forms["fp64_fcg_pmg_fp32"] = dict(precond=hx.HX_PC_PMG, pmg=mg32.value)
     ref = None
     for name, o in forms.items():
         print(f"[bench] solve {name}", file=sys.stderr, flush=True)
@@ -165,7 +168,9 @@ def solves(pr, mass_pr, maxit=20000):
                                                    2))
     out["fp64_fcg_pmg"].update(degrees=pmg_degrees(pr.p), hierarchy_setup_seconds=round(mg_setup, 3),
                                opts={k: getattr(hx.hx_pmg_opts_default(), k) for k, _ in hx.hx_pmg_opts._fields_})
+    out["fp64_fcg_pmg_fp32"].update(degrees=pmg_degrees(pr.p), hierarchy_setup_seconds=round(mg32_setup, 3))
     pmg_close(mg, coarse)
+    pmg_close(mg32, coarse32)
     return out
 
 
@@ -244,6 +249,11 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512))
     _, out["fp64_fcg_pmg"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
     out["fp64_fcg_pmg"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+    pmg_close(mg, coarse)
+    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512),
+                                         prec=hx.HX_FP32)
+    _, out["fp64_fcg_pmg_fp32"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+    out["fp64_fcg_pmg_fp32"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
     pmg_close(mg, coarse)
     pr.close()
     return out

@@ -408,10 +408,15 @@ typedef struct {
   int coarse_maxit;    /* Jacobi-PCG iteration cap on the coarsest level (>= 1) */
   double coarse_rtol;  /* coarse PCG tolerance relative to its right-hand side;
                           0: exactly coarse_maxit iterations (a fixed map)       */
+  int prec;            /* HX_FP64, or HX_FP32: the V-cycle's vectors, operators
+                          (FP32 copies of the geometric factors, made at
+                          creation) and smoothers in FP32, the transfers'
+                          contractions and every reduction in FP64; the
+                          V-cycle's input and output stay FP64                  */
 } hx_pmg_opts;
 
 /* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 30,
- * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations). */
+ * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations), HX_FP64. */
 void hx_pmg_opts_default(hx_pmg_opts *opts);
 
 /* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):

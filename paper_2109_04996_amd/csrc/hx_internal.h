@@ -165,12 +165,14 @@ struct hx_pmg_s {
     double lam_max = 0.0;
     int64_t applies = 0;      // operator applies made by V-cycles on this level
     hx::DevBuf<double> work;  // 10 n: the level's vectors
+    hx::DevBuf<float> work32; // 10 n: the level's FP32 vectors (FP32 V-cycle)
     hx::DevBuf<double> red;   // reduction partials and device scalars of its solves
     // transfer from level l+1 (coarse) to this level (fine); empty on the coarsest level
     int Pc = 0;
     hx::DevBuf<double> interp;     // [Pf][Pc]: coarse Lagrange basis at the fine GLL nodes
     hx::DevBuf<int32_t> cmap;      // [E] fine internal position -> coarse internal position
-    hx::DevBuf<double> ecoarse;    // [E][Pc^3] coarse E-vector of a restriction (coarse internal order)
+    hx::DevBuf<double> ecoarse;    // [E][Pc^3] coarse E-vector of a restriction (coarse internal order; FP32 ones
+                                   // use the front half)
     hx::DevBuf<int64_t> csr_ptr;   // [n_coarse + 1]
     hx::DevBuf<int32_t> csr_slot;  // E-vector slots of each coarse node, ascending
   };
@@ -208,9 +210,12 @@ hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyA
 hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s, int *bad_det);
 hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
 hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s);
-// p-multigrid transfer between level l (fine) and l+1; fm: free mask applied to the output, or null
-hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf, const uint8_t *fm, hipStream_t s);
-hx_status launch_restrict(const hx_pmg_s &mg, int l, const double *rf, double *yc, const uint8_t *fm, hipStream_t s);
+// p-multigrid transfer between level l (fine) and l+1 on FP64 or FP32 vectors; fm: free mask applied to the
+// output, or null
+template <typename T>
+hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const uint8_t *fm, hipStream_t s);
+template <typename T>
+hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s);
 // each level's diagonal and lam_max (solver side)
 hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s);
 

@@ -42,12 +42,13 @@ __device__ __forceinline__ int32_t fine_node(const int32_t *__restrict__ idx_f, 
   }
 }
 
-template <bool AFF>
+// T: the vectors' type (the contractions run in FP64 either way)
+template <bool AFF, typename T>
 __global__ void __launch_bounds__(kTW * 64)
 k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
           const int32_t *__restrict__ aff, const int32_t *__restrict__ idx_c, const uint16_t *__restrict__ own,
-          const double *__restrict__ I, const uint8_t *__restrict__ fm, const double *__restrict__ xc,
-          double *__restrict__ yf) {
+          const double *__restrict__ I, const uint8_t *__restrict__ fm, const T *__restrict__ xc,
+          T *__restrict__ yf) {
   extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -56,7 +57,7 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
   const int Pc3 = Pc * Pc * Pc, Pf2 = Pf * Pf, Pf3 = Pf2 * Pf;
   if (live) {
     const int64_t ec = cmap[e];
-    for (int t = l; t < Pc3; t += 64) A[t] = xc[idx_c[ec * Pc3 + t]];
+    for (int t = l; t < Pc3; t += 64) A[t] = (double)xc[idx_c[ec * Pc3 + t]];
   }
   __syncthreads();
   if (live)  // r1: B[k][j][i] = sum_a I[i][a] A[k][j][a]   (k, j < Pc; i < Pf)
@@ -82,16 +83,16 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
       for (int c = 0; c < Pc; ++c) v += I[k * Pc + c] * A[c * Pf2 + ji];
       if ((own[e * Pf2 + ji] >> k) & 1) {
         const int32_t node = fine_node<AFF>(idx_f, aff, e, Pf, ji, k);
-        yf[node] = (fm && !fm[node]) ? 0.0 : v;
+        yf[node] = (fm && !fm[node]) ? T(0) : (T)v;
       }
     }
 }
 
-template <bool AFF>
+template <bool AFF, typename T>
 __global__ void __launch_bounds__(kTW * 64)
 k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
                 const int32_t *__restrict__ aff, const uint16_t *__restrict__ own, const double *__restrict__ I,
-                const double *__restrict__ rf, double *__restrict__ ec_out) {
+                const T *__restrict__ rf, T *__restrict__ ec_out) {
   extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -101,7 +102,7 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
   if (live)
     for (int t = l; t < Pf3; t += 64) {
       const int ji = t % Pf2, k = t / Pf2;
-      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? rf[fine_node<AFF>(idx_f, aff, e, Pf, ji, k)] : 0.0;
+      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? (double)rf[fine_node<AFF>(idx_f, aff, e, Pf, ji, k)] : 0.0;
     }
   __syncthreads();
   if (live)  // r3: B[c][j][i] = sum_k I[k][c] A[k][j][i]   (c < Pc; j, i < Pf)
@@ -126,18 +127,19 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
       const int a = t % Pc, cb = t / Pc;
       double v = 0.0;
       for (int i = 0; i < Pf; ++i) v += I[i * Pc + a] * A[cb * Pf + i];
-      ec_out[ec * Pc3 + t] = v;
+      ec_out[ec * Pc3 + t] = (T)v;
     }
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
 k_restrict_sum(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ slot,
-               const double *__restrict__ ev, const uint8_t *__restrict__ fm, double *__restrict__ y) {
+               const T *__restrict__ ev, const uint8_t *__restrict__ fm, T *__restrict__ y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double v = 0.0;
-    for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) v += ev[slot[s]];
-    y[i] = (fm && !fm[i]) ? 0.0 : v;
+    for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) v += (double)ev[slot[s]];
+    y[i] = (fm && !fm[i]) ? T(0) : (T)v;
   }
 }
 
@@ -145,41 +147,49 @@ int64_t blocks_for(int64_t E) { return (E + kTW - 1) / kTW; }
 
 }  // namespace
 
-hx_status launch_prolong(const hx_pmg_s &mg, int l, const double *xc, double *yf, const uint8_t *fm, hipStream_t s) {
+template <typename T>
+hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const uint8_t *fm, hipStream_t s) {
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem == 0) return HX_OK;
   const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
   const size_t lds = sizeof(double) * kTW * (prolong_lds_a(mf->P, F.Pc) + prolong_lds_b(mf->P, F.Pc));
   if (mf->idx_affine.count)
-    hipLaunchKernelGGL(k_prolong<true>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+    hipLaunchKernelGGL((k_prolong<true, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                        mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
   else
-    hipLaunchKernelGGL(k_prolong<false>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+    hipLaunchKernelGGL((k_prolong<false, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
                        mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
 
-hx_status launch_restrict(const hx_pmg_s &mg, int l, const double *rf, double *yc, const uint8_t *fm, hipStream_t s) {
+template <typename T>
+hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s) {
+  T *ev = reinterpret_cast<T *>(mg.lv[l]->ecoarse.ptr);  // FP64 storage, large enough for either type
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem > 0) {
     const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
     const size_t lds = sizeof(double) * kTW * (restrict_lds_a(mf->P, F.Pc) + restrict_lds_b(mf->P, F.Pc));
     if (mf->idx_affine.count)
-      hipLaunchKernelGGL(k_restrict_elem<true>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
+      hipLaunchKernelGGL((k_restrict_elem<true, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, ev);
     else
-      hipLaunchKernelGGL(k_restrict_elem<false>, g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, F.ecoarse.ptr);
+      hipLaunchKernelGGL((k_restrict_elem<false, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, ev);
   }
   const int64_t nc = mc->nnodes;
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nc + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_restrict_sum, dim3(nb), dim3(256), 0, s, nc, F.csr_ptr.ptr, F.csr_slot.ptr, F.ecoarse.ptr, fm, yc);
+  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(nb), dim3(256), 0, s, nc, F.csr_ptr.ptr, F.csr_slot.ptr, ev, fm, yc);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
+
+template hx_status launch_prolong<double>(const hx_pmg_s &, int, const double *, double *, const uint8_t *, hipStream_t);
+template hx_status launch_prolong<float>(const hx_pmg_s &, int, const float *, float *, const uint8_t *, hipStream_t);
+template hx_status launch_restrict<double>(const hx_pmg_s &, int, const double *, double *, const uint8_t *, hipStream_t);
+template hx_status launch_restrict<float>(const hx_pmg_s &, int, const float *, float *, const uint8_t *, hipStream_t);
 
 }  // namespace hx
 
@@ -247,6 +257,7 @@ extern "C" void hx_pmg_opts_default(hx_pmg_opts *o) {
   o->lanczos_steps = 20;
   o->coarse_maxit = 30;
   o->coarse_rtol = 0.1;
+  o->prec = HX_FP64;
 }
 
 extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream stream,
@@ -259,6 +270,7 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
       !(o.coarse_rtol >= 0.0 && o.coarse_rtol < 1.0))
     return fail(HX_EINVAL, "need smooth_degree >= 1, smooth_ratio > 1, lanczos_steps >= 2, coarse_maxit >= 1, "
                            "0 <= coarse_rtol < 1");
+  if (o.prec != HX_FP64 && o.prec != HX_FP32) return fail(HX_EINVAL, "prec must be HX_FP64 or HX_FP32");
   for (int l = 0; l < nlevels; ++l) {
     if (!ops[l]) return fail(HX_EINVAL, "null operator in ops");
     if (ops[l]->ncomp != 1) return fail(HX_EUNSUPPORTED, "p-multigrid supports scalar operators only");

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <functional>
 #include <random>
+#include <type_traits>
 
 #include "mlp_internal.h"
 
@@ -274,10 +275,11 @@ __global__ void __launch_bounds__(kVecThreads) k_jac_add(int64_t n, const double
 }
 
 // w = m (r - w): masked residual, in place over w = A z
-__global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, const double *__restrict__ r,
-                                                          const uint8_t *__restrict__ fm, double *__restrict__ w) {
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, const T *__restrict__ r,
+                                                          const uint8_t *__restrict__ fm, T *__restrict__ w) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] = fm[i] ? r[i] - w[i] : 0.0;
+    w[i] = fm[i] ? r[i] - w[i] : T(0);
 }
 
 // Chebyshev step with a general base map: d = a d + b m, z += d (k == 0: d = b m, z = d)
@@ -427,7 +429,7 @@ hx_status cheb_apply_base(Ctx &c, const Cheb &ch, const Vecs<double> &v, const P
   LAUNCH_V(k_cheb_m, c.n, 0.0, 1.0 / theta, v.m, v.cd, z, 1);
   for (int k = 1; k < ch.degree; ++k) {
     if (hx_status st = apply_T(c, z, v.ct, HX_FP64)) return st;
-    LAUNCH_V(k_mresid, c.n, r, c.op.mesh->freemask.ptr, v.ct);
+    LAUNCH_V((k_mresid<double>), c.n, r, c.op.mesh->freemask.ptr, v.ct);
     if (hx_status st = base(v.ct, v.m)) return st;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     LAUNCH_V(k_cheb_m, c.n, rho_new * rho, 2.0 * rho_new / delta, v.m, v.cd, z, 0);
@@ -649,21 +651,35 @@ Ctx level_ctx(hx_pmg_s &mg, hx_pmg_s::Level &L, hipStream_t s) {
   return Ctx{*L.op, s, L.n, 1, red, red + kVecBlocks, red + 3 * kVecBlocks, red + 2 * kVecBlocks, mg.hS, 0};
 }
 
-// z = V_l r. Level l's vectors: r and z are the caller's at level 0 and v.r, v.x below it; the level
+// the level's work vectors of type T (carved at setup)
+hx_status level_vecs(hx_pmg_s::Level &L, Vecs<double> &v) { return carve(L.work, L.n, v); }
+hx_status level_vecs(hx_pmg_s::Level &L, Vecs<float> &v) { return carve(L.work32, L.n, v); }
+
+// x += d
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_add(int64_t n, const T *__restrict__ d, T *__restrict__ x) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    x[t] += d[t];
+}
+
+// z = V_l r on vectors of type T (operators in the matching precision: FP32 ones read FP32 geometric
+// factors). Level l's vectors: r and z are the caller's at level 0 and v.r, v.x below it; the level
 // itself uses v.w, v.p, v.cd, v.ct and v.dinv. The coarsest level runs Jacobi-PCG from 0.
-hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStream_t s) {
+template <typename T>
+hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
+  constexpr int op_prec = std::is_same<T, float>::value ? HX_FP32 : HX_FP64;
   auto &L = *mg.lv[l];
   Ctx c = level_ctx(mg, L, s);
-  Vecs<double> v;
-  if (hx_status st = carve(L.work, L.n, v)) return st;
+  Vecs<T> v;
+  if (hx_status st = level_vecs(L, v)) return st;
   const int64_t n = L.n;
   if (l + 1 == mg.lv.size()) {
-    if (r != v.r) HX_HIP(hipMemcpyAsync(v.r, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (r != v.r) HX_HIP(hipMemcpyAsync(v.r, r, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
     double rr0 = 1.0, stop2 = 0.0;
     int check = mg.opts.coarse_maxit;
     if (mg.opts.coarse_rtol > 0.0) {
       HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, s));
-      LAUNCH_V((k_dot<double>), n, v.r, v.r, c.part0);
+      LAUNCH_V((k_dot<T>), n, v.r, v.r, c.part0);
       FINAL(c.part0, (const double *)nullptr, FIN_SUM, S_TMP);
       if (hx_status st = read_scalars(c)) return st;
       rr0 = c.hS[S_TMP];
@@ -672,13 +688,13 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStrea
     }
     int it = 0;
     double rr = 0.0;
-    hx_status st = rr0 > 0.0 ? pcg_core<double>(c, v, nullptr, HX_FP64, rr0, stop2, mg.opts.coarse_maxit, check,
-                                                false, &it, &rr)
-                             : (hipMemsetAsync(v.x, 0, sizeof(double) * n, s) == hipSuccess ? HX_OK : HX_EHIP);
+    hx_status st = rr0 > 0.0 ? pcg_core<T>(c, v, nullptr, op_prec, rr0, stop2, mg.opts.coarse_maxit, check, false,
+                                           &it, &rr)
+                             : (hipMemsetAsync(v.x, 0, sizeof(T) * n, s) == hipSuccess ? HX_OK : HX_EHIP);
     if (st == HX_EBREAKDOWN) st = HX_OK;  // keep the iterate reached (a residual that vanished exactly)
     L.applies += c.applies;
     if (st) return st;
-    if (z != v.x) HX_HIP(hipMemcpyAsync(z, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (z != v.x) HX_HIP(hipMemcpyAsync(z, v.x, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
     return HX_OK;
   }
   const uint8_t *fm = L.op->mesh->freemask.ptr;
@@ -687,30 +703,46 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const double *r, double *z, hipStrea
   ch.lam_hi = 1.1 * L.lam_max;
   ch.lam_lo = ch.lam_hi / mg.opts.smooth_ratio;
   auto &C = *mg.lv[l + 1];
-  Vecs<double> vc;
-  if (hx_status st = carve(C.work, C.n, vc)) return st;
+  Vecs<T> vc;
+  if (hx_status st = level_vecs(C, vc)) return st;
   // pre-smoothing from 0, then the masked residual
-  if (hx_status st = cheb_apply<double>(c, ch, v, r, z, HX_FP64)) return st;
-  if (hx_status st = apply_T(c, z, v.w, HX_FP64)) return st;
-  LAUNCH_V(k_mresid, n, r, fm, v.w);
+  if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
+  if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
+  LAUNCH_V((k_mresid<T>), n, r, fm, v.w);
   // coarse correction
-  if (hx_status st = launch_restrict(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s)) return st;
-  if (hx_status st = pmg_level(mg, l + 1, vc.r, vc.x, s)) return st;
-  if (hx_status st = launch_prolong(mg, (int)l, vc.x, v.w, fm, s)) return st;
-  LAUNCH_V((k_axpy<double>), n, 1.0, v.w, z);
+  if (hx_status st = launch_restrict<T>(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s)) return st;
+  if (hx_status st = pmg_level<T>(mg, l + 1, vc.r, vc.x, s)) return st;
+  if (hx_status st = launch_prolong<T>(mg, (int)l, vc.x, v.w, fm, s)) return st;
+  LAUNCH_V((k_add<T>), n, v.w, z);
   // post-smoothing on the new residual
-  if (hx_status st = apply_T(c, z, v.w, HX_FP64)) return st;
-  LAUNCH_V(k_mresid, n, r, fm, v.w);
-  if (hx_status st = cheb_apply<double>(c, ch, v, v.w, v.p, HX_FP64)) return st;
-  LAUNCH_V((k_axpy<double>), n, 1.0, v.p, z);
+  if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
+  LAUNCH_V((k_mresid<T>), n, r, fm, v.w);
+  if (hx_status st = cheb_apply<T>(c, ch, v, v.w, v.p, op_prec)) return st;
+  LAUNCH_V((k_add<T>), n, v.p, z);
   L.applies += c.applies;
+  HX_HIP(hipGetLastError());
+  return HX_OK;
+}
+
+// z = V_0 r on FP64 vectors; an FP32 hierarchy converts at the finest level (its v.m and v.rp carry
+// the FP32 input and output: the level itself does not use them)
+hx_status pmg_vcycle(hx_pmg_s &mg, const double *r, double *z, hipStream_t s) {
+  if (mg.opts.prec == HX_FP64) return pmg_level<double>(mg, 0, r, z, s);
+  auto &L = *mg.lv[0];
+  Ctx c = level_ctx(mg, L, s);
+  Vecs<float> v;
+  if (hx_status st = level_vecs(L, v)) return st;
+  LAUNCH_V((k_convert<double, float>), L.n, 1.0, r, v.m);
+  if (hx_status st = pmg_level<float>(mg, 0, v.m, v.rp, s)) return st;
+  LAUNCH_V((k_convert<float, double>), L.n, 1.0, v.rp, z);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
 
 }  // namespace
 
-// each level's work vectors, D^-1 and (above the coarsest) lam_max of D^-1 A by Lanczos
+// each level's work vectors, D^-1 and (above the coarsest) lam_max of D^-1 A by Lanczos; an FP32
+// hierarchy also gets FP32 vectors, D^-1 and geometric factors
 hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
   if (!mg.hS) HX_HIP(hipHostMalloc(reinterpret_cast<void **>(&mg.hS), sizeof(double) * S_NSCAL));
   for (size_t l = 0; l < mg.lv.size(); ++l) {
@@ -727,6 +759,12 @@ hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
     Ctx c = level_ctx(mg, L, s);
     LAUNCH_V((k_dinv<double, 1>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
     HX_HIP(hipGetLastError());
+    if (mg.opts.prec == HX_FP32) {
+      Vecs<float> v32;
+      if (hx_status st = carve(L.work32, L.n, v32)) return st;
+      LAUNCH_V((k_convert<double, float>), L.n, 1.0, v.dinv, v32.dinv);
+      if (hx_status st = make_qdata32(op, s)) return st;
+    }
     if (l + 1 < mg.lv.size())
       if (hx_status st = lanczos_lambda_max(c, v, mg.opts.lanczos_steps, &L.lam_max)) return st;
   }
@@ -739,7 +777,7 @@ hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
 extern "C" hx_status hx_pmg_vcycle(hx_pmg mg, const double *r, double *z, hx_stream s) {
   if (!mg || !r || !z) return hx::fail(HX_EINVAL, "null argument");
   if (r == z) return hx::fail(HX_EINVAL, "z must not alias r");
-  return hx::pmg_level(*mg, 0, r, z, static_cast<hipStream_t>(s));
+  return hx::pmg_vcycle(*mg, r, z, static_cast<hipStream_t>(s));
 }
 
 using namespace hx;
@@ -940,7 +978,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       if (o.mlp_mode == 1) return mlp_base(r, z);
       return cheb_apply_base(c, chm, v, mlp_base, r, z);
     };
-    PrecFn<double> pcp = [&](const double *r, double *z) -> hx_status { return pmg_level(*o.pmg, 0, r, z, s); };
+    PrecFn<double> pcp = [&](const double *r, double *z) -> hx_status { return pmg_vcycle(*o.pmg, r, z, s); };
     const PrecFn<double> *pc_cheb = cheb ? ((o.cheb_prec == HX_FP64) ? &pc64 : &pc32) : nullptr;
     const PrecFn<double> *pc = mlp ? &pcm : pmg ? &pcp : pc_cheb;
     const double stop2 = o.rtol * o.rtol * bb;

@@ -123,7 +123,8 @@ def test_solve_opts_defaults(lib):
 
 def test_pmg_opts_defaults(lib):
     o = hx.hx_pmg_opts_default()
-    assert (o.smooth_degree, o.smooth_ratio, o.lanczos_steps, o.coarse_maxit, o.coarse_rtol) == (3, 15.0, 20, 30, 0.1)
+    assert (o.smooth_degree, o.smooth_ratio, o.lanczos_steps, o.coarse_maxit, o.coarse_rtol, o.prec) == \
+        (3, 15.0, 20, 30, 0.1, hx.HX_FP64)
     assert hx.hx_solve_opts_default().pmg is None
     with pytest.raises(AttributeError):
         hx.hx_pmg_opts_default(not_a_field=1)
