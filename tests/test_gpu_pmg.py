@@ -34,7 +34,8 @@ def _meshes(N, degrees, warp, frac, seed=0):
 
 @pytest.mark.parametrize("N,degrees,warp,frac", [(5, (4, 2), "B", 0.2), (4, (7, 3, 1), "A", 0.0),
                                                  (3, (8, 4), "B", 0.3), (9, (2, 1), "B", 0.2),
-                                                 (3, (6, 5), "A", 0.0)])
+                                                 (3, (6, 5), "A", 0.0), (1, (4, 2), "A", 0.0),
+                                                 (2, (3, 1), "B", 0.0)])
 def test_transfers_match_oracle(N, degrees, warp, frac):
     print(f"\n[case] pmg transfers N={N} degrees={degrees} warp={warp} rotated={frac}", flush=True)
     ms = _meshes(N, degrees, warp, frac)
@@ -57,6 +58,8 @@ def test_transfers_match_oracle(N, degrees, warp, frac):
 
 @pytest.mark.parametrize("N,degrees,rule,kind,warp,frac", [(4, (4, 2, 1), "gll", "diffusion", "B", 0.2),
                                                            (3, (7, 3), "gll", "diffusion", "A", 0.0),
+                                                           # one element: the coarsest level has no free node
+                                                           (1, (4, 2, 1), "gll", "diffusion", "A", 0.0),
                                                            (3, (5, 2, 1), "gauss", "diffusion", "B", 0.0),
                                                            (4, (3, 1), "gauss", "mass", "B", 0.0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -78,7 +81,9 @@ def test_vcycle_matches_oracle(N, degrees, rule, kind, warp, frac, prec):
                 assert 0.9 * lam_ref <= lam <= lam_ref * (1 + 1e-12), (lam, lam_ref)
             levels.append(pmg.Level(A, free, lam, P))
         r = uniform_vector(ms[0]["nnodes"], 5) * levels[0].f
-        z = H.vcycle(H.fine.to_dev(r)).cpu().numpy()
+        zd = H.vcycle(H.fine.to_dev(r))
+        assert torch.equal(zd, H.vcycle(H.fine.to_dev(r)))  # the same bits twice
+        z = zd.cpu().numpy()
         zr = pmg.vcycle(levels, r, degree=3, ratio=15.0, coarse_rtol=0.0, coarse_maxit=8)
         assert np.all(z[~levels[0].free] == 0)
         # FP32: single-precision smoothers and an 8-step FP32 coarse CG (FP64 reductions and transfers)
