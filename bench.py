@@ -105,7 +105,7 @@ def pmg_hierarchy(pr, rule, warp="A", shuffle_seed=0, kappa=None, **opts):
     from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd.problem import Problem
     t0 = time.perf_counter()
-    coarse = [Problem(pr.N, pc, pc + 1 if rule == "gll" else pc + 2, rule, pr.kind, warp=warp,
+    coarse = [Problem(pr.N, pc, pc + 1 if rule == "gll" else pc + 2, rule, pr.kind, ncomp=pr.ncomp, warp=warp,
                       shuffle_seed=shuffle_seed, kappa=kappa) for pc in pmg_degrees(pr.p)[1:]]
     h = hx.hx_pmg_create([pr.h_op] + [c.h_op for c in coarse], hx.hx_pmg_opts_default(**opts))
     return h, coarse, time.perf_counter() - t0
@@ -215,6 +215,11 @@ def suite_vector_ir(p=6, N=30):
     _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
     _, out["ir_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP64)
     _, out["ir_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP32)
+    for name, prec in (("fp64_fcg_pmg", hx.HX_FP64), ("fp64_fcg_pmg_fp32", hx.HX_FP32)):
+        mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", prec=prec)
+        _, out[name] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+        out[name].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+        pmg_close(mg, coarse)
     pr.close()
     return out
 

@@ -420,13 +420,15 @@ typedef struct {
 void hx_pmg_opts_default(hx_pmg_opts *opts);
 
 /* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):
- * 2 <= nlevels <= 8, every operator scalar (ncomp 1) and of one kind, degrees
+ * 2 <= nlevels <= 8, every operator of one kind and one ncomp (the transfers act on
+ * each interleaved component; the coarse PCG is one CG on all of them), degrees
  * strictly decreasing, meshes with the same elements in the same caller order and
  * the same corner positions (element e of every level is the same hexahedron in
  * the same local orientation), every node in some element. Computes each level's
- * diagonal and lam_max on s and returns after they are done. Errors: HX_EINVAL
- * (arguments, mismatched levels), HX_EUNSUPPORTED (vector operators), HX_ENOMEM,
- * HX_EHIP, HX_EBREAKDOWN (a lam_max estimate failed). */
+ * diagonal and lam_max on s and returns after they are done. The hierarchy keeps
+ * work vectors per level: calls that use one hierarchy (V-cycles, solves) must not
+ * overlap. Errors: HX_EINVAL (arguments, mismatched levels), HX_ENOMEM, HX_EHIP,
+ * HX_EBREAKDOWN (a lam_max estimate failed). */
 hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream s, hx_pmg *out);
 int hx_pmg_levels(hx_pmg mg);
 /* lam_max of D_l^-1 A_l as estimated at creation (0 for the coarsest level). */

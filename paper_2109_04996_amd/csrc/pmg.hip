@@ -47,8 +47,9 @@ template <bool AFF, typename T>
 __global__ void __launch_bounds__(kTW * 64)
 k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
           const int32_t *__restrict__ aff, const int32_t *__restrict__ idx_c, const uint16_t *__restrict__ own,
-          const double *__restrict__ I, const uint8_t *__restrict__ fm, const T *__restrict__ xc,
+          const double *__restrict__ I, const uint8_t *__restrict__ fm, int nc, const T *__restrict__ xc,
           T *__restrict__ yf) {
+  const int comp = blockIdx.y;  // component of an interleaved vector (node * nc + comp)
   extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -57,7 +58,7 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
   const int Pc3 = Pc * Pc * Pc, Pf2 = Pf * Pf, Pf3 = Pf2 * Pf;
   if (live) {
     const int64_t ec = cmap[e];
-    for (int t = l; t < Pc3; t += 64) A[t] = (double)xc[idx_c[ec * Pc3 + t]];
+    for (int t = l; t < Pc3; t += 64) A[t] = (double)xc[(int64_t)idx_c[ec * Pc3 + t] * nc + comp];
   }
   __syncthreads();
   if (live)  // r1: B[k][j][i] = sum_a I[i][a] A[k][j][a]   (k, j < Pc; i < Pf)
@@ -83,7 +84,7 @@ k_prolong(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int
       for (int c = 0; c < Pc; ++c) v += I[k * Pc + c] * A[c * Pf2 + ji];
       if ((own[e * Pf2 + ji] >> k) & 1) {
         const int32_t node = fine_node<AFF>(idx_f, aff, e, Pf, ji, k);
-        yf[node] = (fm && !fm[node]) ? T(0) : (T)v;
+        yf[(int64_t)node * nc + comp] = (fm && !fm[node]) ? T(0) : (T)v;
       }
     }
 }
@@ -92,7 +93,8 @@ template <bool AFF, typename T>
 __global__ void __launch_bounds__(kTW * 64)
 k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
                 const int32_t *__restrict__ aff, const uint16_t *__restrict__ own, const double *__restrict__ I,
-                const T *__restrict__ rf, T *__restrict__ ec_out) {
+                int nc, const T *__restrict__ rf, T *__restrict__ ec_out) {
+  const int comp = blockIdx.y;
   extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * kTW + w;
@@ -102,7 +104,8 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
   if (live)
     for (int t = l; t < Pf3; t += 64) {
       const int ji = t % Pf2, k = t / Pf2;
-      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? (double)rf[fine_node<AFF>(idx_f, aff, e, Pf, ji, k)] : 0.0;
+      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? (double)rf[(int64_t)fine_node<AFF>(idx_f, aff, e, Pf, ji, k) * nc + comp]
+                                            : 0.0;
     }
   __syncthreads();
   if (live)  // r3: B[c][j][i] = sum_k I[k][c] A[k][j][i]   (c < Pc; j, i < Pf)
@@ -127,20 +130,21 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
       const int a = t % Pc, cb = t / Pc;
       double v = 0.0;
       for (int i = 0; i < Pf; ++i) v += I[i * Pc + a] * A[cb * Pf + i];
-      ec_out[ec * Pc3 + t] = (T)v;
+      ec_out[(comp * E + ec) * Pc3 + t] = (T)v;
     }
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_restrict_sum(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ slot,
+k_restrict_sum(int64_t n, int nc, int64_t ev_stride, const int64_t *__restrict__ ptr, const int32_t *__restrict__ slot,
                const T *__restrict__ ev, const uint8_t *__restrict__ fm, T *__restrict__ y) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) v += (double)ev[slot[s]];
-    y[i] = (fm && !fm[i]) ? T(0) : (T)v;
-  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int c = 0; c < nc; ++c) {
+      double v = 0.0;
+      for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) v += (double)ev[c * ev_stride + slot[s]];
+      y[i * nc + c] = (fm && !fm[i]) ? T(0) : (T)v;
+    }
 }
 
 int64_t blocks_for(int64_t E) { return (E + kTW - 1) / kTW; }
@@ -152,14 +156,15 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const ui
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem == 0) return HX_OK;
-  const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+  const int nc = F.op->ncomp;
+  const dim3 g((unsigned)blocks_for(mf->nelem), (unsigned)nc), b(kTW * 64);
   const size_t lds = sizeof(double) * kTW * (prolong_lds_a(mf->P, F.Pc) + prolong_lds_b(mf->P, F.Pc));
   if (mf->idx_affine.count)
     hipLaunchKernelGGL((k_prolong<true, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
+                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, nc, xc, yf);
   else
     hipLaunchKernelGGL((k_prolong<false, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, xc, yf);
+                       mf->idx_affine.ptr, mc->idx.ptr, mf->own.ptr, F.interp.ptr, fm, nc, xc, yf);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -167,21 +172,22 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const ui
 template <typename T>
 hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s) {
   T *ev = reinterpret_cast<T *>(mg.lv[l]->ecoarse.ptr);  // FP64 storage, large enough for either type
+  const int nc = mg.lv[l]->op->ncomp;
   const auto &F = *mg.lv[l];
   const hx_mesh mf = F.op->mesh, mc = mg.lv[l + 1]->op->mesh;
   if (mf->nelem > 0) {
-    const dim3 g((unsigned)blocks_for(mf->nelem)), b(kTW * 64);
+    const dim3 g((unsigned)blocks_for(mf->nelem), (unsigned)nc), b(kTW * 64);
     const size_t lds = sizeof(double) * kTW * (restrict_lds_a(mf->P, F.Pc) + restrict_lds_b(mf->P, F.Pc));
     if (mf->idx_affine.count)
       hipLaunchKernelGGL((k_restrict_elem<true, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, ev);
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, ev);
     else
       hipLaunchKernelGGL((k_restrict_elem<false, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, rf, ev);
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, ev);
   }
-  const int64_t nc = mc->nnodes;
-  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nc + 255) / 256, 4096));
-  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(nb), dim3(256), 0, s, nc, F.csr_ptr.ptr, F.csr_slot.ptr, ev, fm, yc);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((mc->nnodes + 255) / 256, 4096));
+  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(nb), dim3(256), 0, s, mc->nnodes, nc, mf->nelem * (int64_t)F.Pc * F.Pc * F.Pc,
+                     F.csr_ptr.ptr, F.csr_slot.ptr, ev, fm, yc);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -244,7 +250,7 @@ hx_status build_transfer(hx_pmg_s::Level &F, const hx_pmg_s::Level &C) {
   HX_HIP(F.cmap.upload(cmap.data(), cmap.size()));
   HX_HIP(F.csr_ptr.upload(ptr.data(), ptr.size()));
   HX_HIP(F.csr_slot.upload(slot.data(), slot.size()));
-  HX_HIP(F.ecoarse.alloc((size_t)E * Pc3));
+  HX_HIP(F.ecoarse.alloc((size_t)E * Pc3 * F.op->ncomp));
   return HX_OK;
 }
 
@@ -273,7 +279,7 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
   if (o.prec != HX_FP64 && o.prec != HX_FP32) return fail(HX_EINVAL, "prec must be HX_FP64 or HX_FP32");
   for (int l = 0; l < nlevels; ++l) {
     if (!ops[l]) return fail(HX_EINVAL, "null operator in ops");
-    if (ops[l]->ncomp != 1) return fail(HX_EUNSUPPORTED, "p-multigrid supports scalar operators only");
+    if (ops[l]->ncomp != ops[0]->ncomp) return fail(HX_EINVAL, "the levels' operators differ in components");
     if (ops[l]->mesh->nuntouched > 0) return fail(HX_EINVAL, "p-multigrid needs every node in some element");
     if (l == 0) continue;
     if (ops[l]->kind != ops[0]->kind) return fail(HX_EINVAL, "the levels' operators differ in kind");
@@ -286,7 +292,7 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
   for (int l = 0; l < nlevels; ++l) {
     mg->lv.push_back(std::make_unique<hx_pmg_s::Level>());
     mg->lv[l]->op = ops[l];
-    mg->lv[l]->n = ops[l]->mesh->nnodes;
+    mg->lv[l]->n = ops[l]->mesh->nnodes * ops[l]->ncomp;
   }
   for (int l = 0; l + 1 < nlevels; ++l)
     if (hx_status st = build_transfer(*mg->lv[l], *mg->lv[l + 1])) return st;

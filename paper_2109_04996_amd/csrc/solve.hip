@@ -274,12 +274,12 @@ __global__ void __launch_bounds__(kVecThreads) k_jac_add(int64_t n, const double
     z[i] += dinv[i] * r[i];
 }
 
-// w = m (r - w): masked residual, in place over w = A z
+// w = m (r - w): masked residual, in place over w = A z (nc interleaved components share a node's mask)
 template <typename T>
-__global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, const T *__restrict__ r,
+__global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, int nc, const T *__restrict__ r,
                                                           const uint8_t *__restrict__ fm, T *__restrict__ w) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] = fm[i] ? r[i] - w[i] : T(0);
+    w[i] = fm[nc == 1 ? i : i / nc] ? r[i] - w[i] : T(0);
 }
 
 // Chebyshev step with a general base map: d = a d + b m, z += d (k == 0: d = b m, z = d)
@@ -429,7 +429,7 @@ hx_status cheb_apply_base(Ctx &c, const Cheb &ch, const Vecs<double> &v, const P
   LAUNCH_V(k_cheb_m, c.n, 0.0, 1.0 / theta, v.m, v.cd, z, 1);
   for (int k = 1; k < ch.degree; ++k) {
     if (hx_status st = apply_T(c, z, v.ct, HX_FP64)) return st;
-    LAUNCH_V((k_mresid<double>), c.n, r, c.op.mesh->freemask.ptr, v.ct);
+    LAUNCH_V((k_mresid<double>), c.n, 1, r, c.op.mesh->freemask.ptr, v.ct);
     if (hx_status st = base(v.ct, v.m)) return st;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     LAUNCH_V(k_cheb_m, c.n, rho_new * rho, 2.0 * rho_new / delta, v.m, v.cd, z, 0);
@@ -648,7 +648,7 @@ struct PinnedHost {
 
 Ctx level_ctx(hx_pmg_s &mg, hx_pmg_s::Level &L, hipStream_t s) {
   double *red = L.red.ptr;
-  return Ctx{*L.op, s, L.n, 1, red, red + kVecBlocks, red + 3 * kVecBlocks, red + 2 * kVecBlocks, mg.hS, 0};
+  return Ctx{*L.op, s, L.n, L.op->ncomp, red, red + kVecBlocks, red + 3 * kVecBlocks, red + 2 * kVecBlocks, mg.hS, 0};
 }
 
 // the level's work vectors of type T (carved at setup)
@@ -708,7 +708,7 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   // pre-smoothing from 0, then the masked residual
   if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
   if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
-  LAUNCH_V((k_mresid<T>), n, r, fm, v.w);
+  LAUNCH_V((k_mresid<T>), n, c.nc, r, fm, v.w);
   // coarse correction
   if (hx_status st = launch_restrict<T>(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s)) return st;
   if (hx_status st = pmg_level<T>(mg, l + 1, vc.r, vc.x, s)) return st;
@@ -716,7 +716,7 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   LAUNCH_V((k_add<T>), n, v.w, z);
   // post-smoothing on the new residual
   if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
-  LAUNCH_V((k_mresid<T>), n, r, fm, v.w);
+  LAUNCH_V((k_mresid<T>), n, c.nc, r, fm, v.w);
   if (hx_status st = cheb_apply<T>(c, ch, v, v.w, v.p, op_prec)) return st;
   LAUNCH_V((k_add<T>), n, v.p, z);
   L.applies += c.applies;
@@ -757,7 +757,8 @@ hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
       op.diag_valid = true;
     }
     Ctx c = level_ctx(mg, L, s);
-    LAUNCH_V((k_dinv<double, 1>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
+    if (op.ncomp == 1) LAUNCH_V((k_dinv<double, 1>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
+    else LAUNCH_V((k_dinv<double, 3>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
     HX_HIP(hipGetLastError());
     if (mg.opts.prec == HX_FP32) {
       Vecs<float> v32;

@@ -100,19 +100,19 @@ class Problem:
 class Hierarchy:
     """p-multigrid over polynomial degrees on one lattice mesh.
 
-    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, **pmg_opts)``:
+    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, ncomp, **pmg_opts)``:
     level l is a ``Problem`` of degree ``degrees[l]`` (strictly decreasing) with
     q = p + 1 GLL points or q = p + 2 Gauss points, on the same elements (same
     shuffle); ``meshes`` overrides the lattice meshes level by level.
     """
 
     def __init__(self, N: int, degrees, rule: str = "gll", kind: str = "diffusion", warp="A", shuffle_seed=0,
-                 kappa: dict | None = None, meshes=None, **pmg_opts):
+                 kappa: dict | None = None, meshes=None, ncomp: int = 1, **pmg_opts):
         self.levels = []
         for l, p in enumerate(degrees):
             q = p + 1 if rule == "gll" else p + 2
-            self.levels.append(Problem(N, p, q, rule, kind, warp=warp, shuffle_seed=shuffle_seed, kappa=kappa,
-                                       mesh=None if meshes is None else meshes[l]))
+            self.levels.append(Problem(N, p, q, rule, kind, ncomp=ncomp, warp=warp, shuffle_seed=shuffle_seed,
+                                       kappa=kappa, mesh=None if meshes is None else meshes[l]))
         self.h = hx.hx_pmg_create([pr.h_op for pr in self.levels], hx.hx_pmg_opts_default(**pmg_opts))
 
     @property
