@@ -434,7 +434,8 @@ int hx_pmg_levels(hx_pmg mg);
 /* lam_max of D_l^-1 A_l as estimated at creation (0 for the coarsest level). */
 hx_status hx_pmg_lambda_max(hx_pmg mg, int level, double *lam_max);
 /* z = V_0 r (device FP64 L-vectors of level 0; z must not alias r). Synchronises s
- * once per coarse solve (its convergence checks). */
+ * at the coarse solve's convergence checks: once with coarse_rtol 0, otherwise at
+ * most 2 + coarse_maxit / 10 times. */
 hx_status hx_pmg_vcycle(hx_pmg mg, const double *r, double *z, hx_stream s);
 /* y_l = P_l x_{l+1} and y_{l+1} = P_l^T r_l, 0 <= level < nlevels-1 (device FP64
  * L-vectors of the two levels; no masking). Asynchronous. */
