@@ -137,8 +137,10 @@ __device__ __forceinline__ void elem_sync() {
 // value its scatter adds it to (requested before the last contraction: zero where ob says the
 // lane stores first). S0, S1: this element's two LDS buffers. NT: threads per element (64 syncs
 // the wavefront, more a workgroup barrier).
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT>
-__device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict__ S1, int a, int b, bool lane_live,
+// ONEBUF (mass only): S1 is S0, one LDS buffer per element; the two passes that read one layout and
+// write another wait for every read before writing
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false>
+__device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool lane_live,
                                               int64_t e, int c, const TQ *__restrict__ qd, const T *__restrict__ tab,
                                               const T *__restrict__ x, const int32_t (&nid)[P], uint32_t ob,
                                               const T *__restrict__ zero, const T *__restrict__ y, T (&old)[P],
@@ -169,6 +171,7 @@ __device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict_
 #pragma unroll
       for (int j = 0; j < P; ++j) u[j] = S0[AT(an, j, b)];
       interp_fwd<P, Q, T>(tI, u, uq);
+      if constexpr (ONEBUF) elem_sync<NT>();
       if (lane_live && a < P) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) S1[AT(a, q, b)] = uq[q];
@@ -316,6 +319,7 @@ __device__ __forceinline__ void gauss_element(T *__restrict__ S0, T *__restrict_
 #pragma unroll
       for (int q = 0; q < Q; ++q) v[q] = S0[AT(an, q, b)];
       interp_bwd<P, Q, T>(tI, v, z);
+      if constexpr (ONEBUF) elem_sync<NT>();
       if (lane_live && a < P) {
 #pragma unroll
         for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = z[j];
@@ -383,8 +387,11 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
 // face there, element w adds it to its own r1 = +1 face and writes it once. Other nodes follow the
 // strip ownership (store by the first writer in strip order, read-modify-write by later ones).
 // IDX: node ids as in k_colloc_strip (0 per node, 1 per r1-row, 2 affine per element).
+// Mass keeps one LDS buffer per element (ONEBUF), and at q = 9 at most 64 registers: two 16-wavefront
+// workgroups then fit on a CU, against one with two buffers.
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX>
 __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
+    __attribute__((amdgpu_waves_per_eu((MODE == MODE_MASS && Q == 9) ? 8 : 1)))
     k_gauss_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                   const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
                   const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
@@ -392,8 +399,9 @@ __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
   constexpr int NTE = GaussCfg<Q>::NT;  // threads per element
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
   constexpr int BUF = Q * Q * (Q + 1);
+  constexpr bool ONEBUF = MODE == MODE_MASS;
   __shared__ T s0[kStrip][BUF];
-  __shared__ T s1[kStrip][BUF];
+  __shared__ T s1[ONEBUF ? 1 : kStrip][ONEBUF ? 1 : BUF];
   __shared__ T face[kStrip][P2];  // element w's r1 = -1 face, [k][j]
 
   const int tid = threadIdx.x;
@@ -431,8 +439,11 @@ __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
   const uint32_t ob = (live && node_lane && !skip) ? (uint32_t)sown[ee * P2 + b * P + a] : 0xffffu;
 
   T old[P], z[P];
-  gauss_element<P, Q, MODE, NC, T, TQ, NTE>(s0[w], s1[w], a, b, lane_live, ee, c, qd, tab, x, nid, ob, zero, y, old,
-                                            z);
+  T *S1;
+  if constexpr (ONEBUF) S1 = s0[w];
+  else S1 = s1[w];
+  gauss_element<P, Q, MODE, NC, T, TQ, NTE, ONEBUF>(s0[w], S1, a, b, lane_live, ee, c, qd, tab, x, nid, ob, zero, y,
+                                                    old, z);
   T out[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) out[k] = old[k] + z[k];
