@@ -135,3 +135,19 @@ def test_flexible_pcg_with_vcycle():
     assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr)
     _, it_j, _ = solvers.jacobi_pcg(A, b, free, tol=1e-8)
     assert it < it_j / 3
+
+
+def test_vector_vcycle_is_three_scalar_vcycles():
+    # the vector operator is the scalar one on each interleaved component (index 3 node + c); with an
+    # exact coarse solve nothing couples the components, so the expanded V-cycle is three scalar ones
+    meshes, levels = _levels(2, (4, 2, 1))
+    vec = []
+    for lv in levels:
+        P3 = None if lv.P is None else sp.kron(lv.P, sp.identity(3), format="csr")
+        vec.append(pmg.Level(solvers.expand(lv.A_full, 3), np.repeat(lv.free, 3), lv.lam_max, P3))
+    n = levels[0].A.shape[0]
+    r = np.random.default_rng(1).uniform(-1, 1, 3 * n)
+    z = pmg.vcycle(vec, r, degree=3, ratio=15.0, coarse="direct")
+    for c in range(3):
+        zc = pmg.vcycle(levels, r[c::3], degree=3, ratio=15.0, coarse="direct")
+        assert np.max(np.abs(z[c::3] - zc)) <= 1e-13 * np.max(np.abs(zc))
