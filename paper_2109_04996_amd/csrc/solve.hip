@@ -252,6 +252,20 @@ __global__ void __launch_bounds__(kVecThreads) k_cheb(int64_t n, T c1, T c2, con
   }
 }
 
+// first Chebyshev step from a nonzero iterate: d = c2 dinv (r - A z), z += d
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads) k_cheb_first(int64_t n, T c2, const T *__restrict__ dinv,
+                                                              const T *__restrict__ r, const T *__restrict__ az,
+                                                              T *__restrict__ d, T *__restrict__ z) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const T v = c2 * dinv[t] * (r[t] - az[t]);
+    d[t] = v;
+    z[t] += v;
+  }
+}
+
 // dinv = m / diag, or m alone when diag is null (no preconditioner)
 template <typename T, int NC>
 __global__ void __launch_bounds__(kVecThreads) k_dinv(int64_t n, const double *__restrict__ diag,
@@ -408,6 +422,27 @@ hx_status cheb_apply(Ctx &c, const Cheb &ch, const Vecs<T> &v, const T *r, T *z,
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     LAUNCH_V((k_cheb<T>), c.n, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), v.dinv, r, v.ct, v.cd, z);
     rho = rho_new;
+  }
+  HX_HIP(hipGetLastError());
+  return HX_OK;
+}
+
+// The same polynomial on the error equation from the iterate already in z: z += s(D^-1 A) D^-1 (r - A z),
+// degree steps and degree operator applies (the first one forms the residual). Uses v.cd and v.ct.
+template <typename T>
+hx_status cheb_apply_from(Ctx &c, const Cheb &ch, const Vecs<T> &v, const T *r, T *z, int op_prec) {
+  const double theta = 0.5 * (ch.lam_hi + ch.lam_lo), delta = 0.5 * (ch.lam_hi - ch.lam_lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < ch.degree; ++k) {
+    if (hx_status st = apply_T(c, z, v.ct, op_prec)) return st;
+    if (k == 0) {
+      LAUNCH_V((k_cheb_first<T>), c.n, (T)(1.0 / theta), v.dinv, r, v.ct, v.cd, z);
+    } else {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      LAUNCH_V((k_cheb<T>), c.n, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), v.dinv, r, v.ct, v.cd, z);
+      rho = rho_new;
+    }
   }
   HX_HIP(hipGetLastError());
   return HX_OK;
@@ -664,7 +699,7 @@ __global__ void __launch_bounds__(kVecThreads) k_add(int64_t n, const T *__restr
 
 // z = V_l r on vectors of type T (operators in the matching precision: FP32 ones read FP32 geometric
 // factors). Level l's vectors: r and z are the caller's at level 0 and v.r, v.x below it; the level
-// itself uses v.w, v.p, v.cd, v.ct and v.dinv. The coarsest level runs Jacobi-PCG from 0.
+// itself uses v.w, v.cd, v.ct and v.dinv. The coarsest level runs Jacobi-PCG from 0.
 template <typename T>
 hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   constexpr int op_prec = std::is_same<T, float>::value ? HX_FP32 : HX_FP64;
@@ -714,11 +749,8 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   if (hx_status st = pmg_level<T>(mg, l + 1, vc.r, vc.x, s)) return st;
   if (hx_status st = launch_prolong<T>(mg, (int)l, vc.x, v.w, fm, s)) return st;
   LAUNCH_V((k_add<T>), n, v.w, z);
-  // post-smoothing on the new residual
-  if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
-  LAUNCH_V((k_mresid<T>), n, c.nc, r, fm, v.w);
-  if (hx_status st = cheb_apply<T>(c, ch, v, v.w, v.p, op_prec)) return st;
-  LAUNCH_V((k_add<T>), n, v.p, z);
+  // post-smoothing: the same polynomial on the error equation, from the corrected iterate
+  if (hx_status st = cheb_apply_from<T>(c, ch, v, r, z, op_prec)) return st;
   L.applies += c.applies;
   HX_HIP(hipGetLastError());
   return HX_OK;
