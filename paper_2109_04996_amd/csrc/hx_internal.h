@@ -214,8 +214,10 @@ hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, h
 // output, or null
 template <typename T>
 hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const uint8_t *fm, hipStream_t s);
+// rb: when given, the restriction acts on the fine residual m (rb - rf) (m the fine free mask)
 template <typename T>
-hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s);
+hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s,
+                          const T *rb = nullptr);
 // each level's diagonal and lam_max (solver side)
 hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s);
 

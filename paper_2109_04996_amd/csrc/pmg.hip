@@ -93,7 +93,8 @@ template <bool AFF, typename T>
 __global__ void __launch_bounds__(kTW * 64)
 k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, const int32_t *__restrict__ idx_f,
                 const int32_t *__restrict__ aff, const uint16_t *__restrict__ own, const double *__restrict__ I,
-                int nc, const T *__restrict__ rf, T *__restrict__ ec_out) {
+                int nc, const T *__restrict__ rf, const T *__restrict__ rb, const uint8_t *__restrict__ fmf,
+                T *__restrict__ ec_out) {
   const int comp = blockIdx.y;
   extern __shared__ double smem[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -104,8 +105,14 @@ k_restrict_elem(int64_t E, int Pf, int Pc, const int32_t *__restrict__ cmap, con
   if (live)
     for (int t = l; t < Pf3; t += 64) {
       const int ji = t % Pf2, k = t / Pf2;
-      A[t] = ((own[e * Pf2 + ji] >> k) & 1) ? (double)rf[(int64_t)fine_node<AFF>(idx_f, aff, e, Pf, ji, k) * nc + comp]
-                                            : 0.0;
+      double v = 0.0;
+      if ((own[e * Pf2 + ji] >> k) & 1) {
+        const int32_t node = fine_node<AFF>(idx_f, aff, e, Pf, ji, k);
+        const int64_t g = (int64_t)node * nc + comp;
+        // rb: restrict the masked residual rb - rf instead of rf
+        v = rb ? (fmf[node] ? (double)rb[g] - (double)rf[g] : 0.0) : (double)rf[g];
+      }
+      A[t] = v;
     }
   __syncthreads();
   if (live)  // r3: B[c][j][i] = sum_k I[k][c] A[k][j][i]   (c < Pc; j, i < Pf)
@@ -170,7 +177,8 @@ hx_status launch_prolong(const hx_pmg_s &mg, int l, const T *xc, T *yf, const ui
 }
 
 template <typename T>
-hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s) {
+hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const uint8_t *fm, hipStream_t s,
+                          const T *rb) {
   T *ev = reinterpret_cast<T *>(mg.lv[l]->ecoarse.ptr);  // FP64 storage, large enough for either type
   const int nc = mg.lv[l]->op->ncomp;
   const auto &F = *mg.lv[l];
@@ -180,10 +188,10 @@ hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const u
     const size_t lds = sizeof(double) * kTW * (restrict_lds_a(mf->P, F.Pc) + restrict_lds_b(mf->P, F.Pc));
     if (mf->idx_affine.count)
       hipLaunchKernelGGL((k_restrict_elem<true, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, ev);
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, rb, mf->freemask.ptr, ev);
     else
       hipLaunchKernelGGL((k_restrict_elem<false, T>), g, b, lds, s, mf->nelem, mf->P, F.Pc, F.cmap.ptr, mf->idx.ptr,
-                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, ev);
+                         mf->idx_affine.ptr, mf->own.ptr, F.interp.ptr, nc, rf, rb, mf->freemask.ptr, ev);
   }
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((mc->nnodes + 255) / 256, 4096));
   hipLaunchKernelGGL((k_restrict_sum<T>), dim3(nb), dim3(256), 0, s, mc->nnodes, nc, mf->nelem * (int64_t)F.Pc * F.Pc * F.Pc,
@@ -194,8 +202,10 @@ hx_status launch_restrict(const hx_pmg_s &mg, int l, const T *rf, T *yc, const u
 
 template hx_status launch_prolong<double>(const hx_pmg_s &, int, const double *, double *, const uint8_t *, hipStream_t);
 template hx_status launch_prolong<float>(const hx_pmg_s &, int, const float *, float *, const uint8_t *, hipStream_t);
-template hx_status launch_restrict<double>(const hx_pmg_s &, int, const double *, double *, const uint8_t *, hipStream_t);
-template hx_status launch_restrict<float>(const hx_pmg_s &, int, const float *, float *, const uint8_t *, hipStream_t);
+template hx_status launch_restrict<double>(const hx_pmg_s &, int, const double *, double *, const uint8_t *, hipStream_t,
+                                           const double *);
+template hx_status launch_restrict<float>(const hx_pmg_s &, int, const float *, float *, const uint8_t *, hipStream_t,
+                                          const float *);
 
 }  // namespace hx
 
@@ -319,7 +329,7 @@ extern "C" hx_status hx_pmg_prolong(hx_pmg mg, int level, const double *x_coarse
 extern "C" hx_status hx_pmg_restrict(hx_pmg mg, int level, const double *r_fine, double *y_coarse, hx_stream s) {
   if (!mg || !r_fine || !y_coarse) return fail(HX_EINVAL, "null argument");
   if (level < 0 || level + 1 >= (int)mg->lv.size()) return fail(HX_EINVAL, "level out of range");
-  return launch_restrict(*mg, level, r_fine, y_coarse, nullptr, static_cast<hipStream_t>(s));
+  return launch_restrict<double>(*mg, level, r_fine, y_coarse, nullptr, static_cast<hipStream_t>(s), nullptr);
 }
 
 extern "C" void hx_pmg_destroy(hx_pmg mg) { delete mg; }

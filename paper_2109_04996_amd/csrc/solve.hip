@@ -740,12 +740,11 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   auto &C = *mg.lv[l + 1];
   Vecs<T> vc;
   if (hx_status st = level_vecs(C, vc)) return st;
-  // pre-smoothing from 0, then the masked residual
+  // pre-smoothing from 0; the restriction reads the masked residual r - A z
   if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
   if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
-  LAUNCH_V((k_mresid<T>), n, c.nc, r, fm, v.w);
   // coarse correction
-  if (hx_status st = launch_restrict<T>(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s)) return st;
+  if (hx_status st = launch_restrict<T>(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s, r)) return st;
   if (hx_status st = pmg_level<T>(mg, l + 1, vc.r, vc.x, s)) return st;
   if (hx_status st = launch_prolong<T>(mg, (int)l, vc.x, v.w, fm, s)) return st;
   LAUNCH_V((k_add<T>), n, v.w, z);
