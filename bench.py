@@ -260,6 +260,12 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     _, out["fp64_fcg_pmg_fp32"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
     out["fp64_fcg_pmg_fp32"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
     pmg_close(mg, coarse)
+    # the FP32 hierarchy with the finest level's operator on the matrix cores (hi + lo bf16 operands)
+    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512),
+                                         prec=hx.HX_BF16_SPLIT)
+    _, out["fp64_fcg_pmg_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+    out["fp64_fcg_pmg_bf16split"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+    pmg_close(mg, coarse)
     pr.close()
     return out
 

@@ -412,7 +412,10 @@ typedef struct {
                           (FP32 copies of the geometric factors, made at
                           creation) and smoothers in FP32, the transfers'
                           contractions and every reduction in FP64; the
-                          V-cycle's input and output stay FP64                  */
+                          V-cycle's input and output stay FP64. HX_BF16 or
+                          HX_BF16_SPLIT: as HX_FP32, with the finest level's
+                          operator on the bf16 matrix cores (hx_op_apply_bf16;
+                          scalar diffusion, p+1 <= 8, q <= 8)                   */
 } hx_pmg_opts;
 
 /* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 30,

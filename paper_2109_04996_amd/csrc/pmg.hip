@@ -286,7 +286,11 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
       !(o.coarse_rtol >= 0.0 && o.coarse_rtol < 1.0))
     return fail(HX_EINVAL, "need smooth_degree >= 1, smooth_ratio > 1, lanczos_steps >= 2, coarse_maxit >= 1, "
                            "0 <= coarse_rtol < 1");
-  if (o.prec != HX_FP64 && o.prec != HX_FP32) return fail(HX_EINVAL, "prec must be HX_FP64 or HX_FP32");
+  if (o.prec != HX_FP64 && o.prec != HX_FP32 && o.prec != HX_BF16 && o.prec != HX_BF16_SPLIT)
+    return fail(HX_EINVAL, "prec must be HX_FP64, HX_FP32, HX_BF16 or HX_BF16_SPLIT");
+  if ((o.prec == HX_BF16 || o.prec == HX_BF16_SPLIT) &&
+      (ops[0]->kind != HX_DIFFUSION || ops[0]->ncomp != 1 || ops[0]->P > 8 || ops[0]->Q > 8))
+    return fail(HX_EUNSUPPORTED, "bf16 p-multigrid needs a scalar diffusion finest level with p+1 <= 8 and q <= 8");
   for (int l = 0; l < nlevels; ++l) {
     if (!ops[l]) return fail(HX_EINVAL, "null operator in ops");
     if (ops[l]->ncomp != ops[0]->ncomp) return fail(HX_EINVAL, "the levels' operators differ in components");

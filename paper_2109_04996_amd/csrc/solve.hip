@@ -702,7 +702,9 @@ __global__ void __launch_bounds__(kVecThreads) k_add(int64_t n, const T *__restr
 // itself uses v.w, v.cd, v.ct and v.dinv. The coarsest level runs Jacobi-PCG from 0.
 template <typename T>
 hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
-  constexpr int op_prec = std::is_same<T, float>::value ? HX_FP32 : HX_FP64;
+  // FP32 hierarchies with a bf16 precision run the finest level's operator on matrix cores
+  const bool mfma = l == 0 && (mg.opts.prec == HX_BF16 || mg.opts.prec == HX_BF16_SPLIT);
+  const int op_prec = std::is_same<T, float>::value ? (mfma ? mg.opts.prec : HX_FP32) : HX_FP64;
   auto &L = *mg.lv[l];
   Ctx c = level_ctx(mg, L, s);
   Vecs<T> v;
@@ -791,11 +793,13 @@ hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
     if (op.ncomp == 1) LAUNCH_V((k_dinv<double, 1>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
     else LAUNCH_V((k_dinv<double, 3>), L.n, op.diag.ptr, op.mesh->freemask.ptr, v.dinv);
     HX_HIP(hipGetLastError());
-    if (mg.opts.prec == HX_FP32) {
+    if (mg.opts.prec != HX_FP64) {
       Vecs<float> v32;
       if (hx_status st = carve(L.work32, L.n, v32)) return st;
       LAUNCH_V((k_convert<double, float>), L.n, 1.0, v.dinv, v32.dinv);
-      if (hx_status st = make_qdata32(op, s)) return st;
+      // FP32 geometric factors, except where the finest level runs on matrix cores (bf16 copy, made on first use)
+      if (mg.opts.prec == HX_FP32 || l > 0)
+        if (hx_status st = make_qdata32(op, s)) return st;
     }
     if (l + 1 < mg.lv.size())
       if (hx_status st = lanczos_lambda_max(c, v, mg.opts.lanczos_steps, &L.lam_max)) return st;

@@ -133,7 +133,9 @@ def test_pmg_rejects_bad_hierarchies():
     with pytest.raises(hx.HexpaError, match="smooth_degree"):
         Hierarchy(N, (2, 1), smooth_degree=0)
     with pytest.raises(hx.HexpaError, match="prec must be"):
-        Hierarchy(N, (2, 1), prec=hx.HX_BF16)
+        Hierarchy(N, (2, 1), prec=7)
+    with pytest.raises(hx.HexpaError, match="bf16 p-multigrid needs"):
+        Hierarchy(N, (2, 1), rule="gauss", kind="mass", prec=hx.HX_BF16)
     with Hierarchy(N, (2, 1)) as H:
         b = H.fine.zeros()
         with pytest.raises(hx.HexpaError, match="needs opts.pmg"):
@@ -199,3 +201,25 @@ def test_vector_pmg_solve():
         assert info["true_rel_residual"] <= 1.05e-8, info
         _, info_j = H.fine.solve(b, rtol=1e-8, check_every=1)
         assert info["iterations"] * 3 < info_j["iterations"], (info["iterations"], info_j["iterations"])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16split"])
+@pytest.mark.parametrize("N,degrees,rule", [(4, (7, 3, 1), "gll"), (4, (6, 3, 1), "gauss")])
+def test_pmg_bf16_finest_level(N, degrees, rule, prec):
+    """An FP32 hierarchy whose finest level smooths on the bf16 matrix cores: the V-cycle stays close to
+    the FP64 one (a smoother needs about one digit) and the FP64 flexible CG still reaches 1e-8."""
+    pv = hx.HX_BF16 if prec == "bf16" else hx.HX_BF16_SPLIT
+    print(f"\n[case] pmg bf16 N={N} degrees={degrees} {rule} {prec}", flush=True)
+    opts = dict(rule=rule, warp="B", coarse_maxit=8, coarse_rtol=0.0)
+    with Hierarchy(N, degrees, **opts) as H64, Hierarchy(N, degrees, prec=pv, **opts) as Hb:
+        r = H64.fine.to_dev(uniform_vector(H64.fine.n, 5) * (H64.fine.mesh["boundary"] == 0))
+        z64 = H64.vcycle(r)
+        zb = Hb.vcycle(r)
+        err = float(torch.linalg.norm(zb - z64) / torch.linalg.norm(z64))
+        assert err <= (1e-1 if prec == "bf16" else 3e-2), err
+        b = _rhs(Hb)
+        _, info = Hb.solve(b, rtol=1e-8, check_every=1)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        _, info64 = H64.solve(b, rtol=1e-8, check_every=1)
+        assert info["iterations"] <= 2 * info64["iterations"] + 2, (info["iterations"], info64["iterations"])
+
