@@ -464,6 +464,8 @@ def main():
     ap.add_argument("--pmc-kernels", action="store_true",
                     help="short run for the FLOP-rate counter pass: 4 applies of each hot kernel (BP5 p=7 FP64 and "
                          "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
+    ap.add_argument("--pmg-sweep", action="store_true",
+                    help="p-multigrid FCG (FP64 and FP32 V-cycles) against Jacobi-PCG on BP5 p=7 over mesh sizes")
     ap.add_argument("--pmg-vcycles", type=int, default=0,
                     help="time this many p-multigrid V-cycles (degrees p, p/2, ..., 1) on the BP5 problem and exit")
     a = ap.parse_args()
@@ -482,6 +484,27 @@ def main():
     torch.cuda.set_device(0)
     if a.sweep:
         sweep()
+        return
+    if a.pmg_sweep:
+        import numpy as np
+        for Ns in (12, 24, 36, 48):
+            print(f"[bench] pmg sweep N={Ns}", file=sys.stderr, flush=True)
+            mesh_s = lattice_mesh(Ns, 7, warp="A", shuffle_seed=0)
+            pr_s = Problem(Ns, 7, 8, "gll", "diffusion", mesh=mesh_s)
+            mass_s = Problem(Ns, 7, 9, "gauss", "mass", mesh=mesh_s)
+            X = pr_s.xyz
+            f = 3 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+            b_s = mass_s.apply(pr_s.to_dev(f))
+            mass_s.close()
+            rec = dict(pmg_sweep="BP5", p=7, N=Ns, dofs=pr_s.n)
+            _, rec["fp64_jacobi"] = _timed_solve(pr_s, b_s)
+            for name, prec in (("fp64_fcg_pmg", hx.HX_FP64), ("fp64_fcg_pmg_fp32", hx.HX_FP32)):
+                mg, coarse, mg_setup = pmg_hierarchy(pr_s, "gll", prec=prec)
+                _, rec[name] = _timed_solve(pr_s, b_s, precond=hx.HX_PC_PMG, pmg=mg.value)
+                rec[name]["hierarchy_setup_seconds"] = round(mg_setup, 3)
+                pmg_close(mg, coarse)
+            print(json.dumps(rec), flush=True)
+            pr_s.close()
         return
     if a.cg_sweep:
         cg_sweep("BP5", 7, 8, "gll")
