@@ -373,7 +373,7 @@ def cg_sweep(label="BP5", p=7, q=8, rule="gll", Ns=CG_SWEEP_N, short=20, long=60
 
 
 def sweep(steps=20, warmup=3):
-    """Apply throughput over the survey's size sweep and the other operator kinds: one JSON line per
+    """Apply throughput over mesh sizes (p = 7, 4, 2) and the other operator kinds: one JSON line per
     case (FP64 operator; FP32-operator figures beside it)."""
     import torch
 
