@@ -223,3 +223,16 @@ def test_pmg_bf16_finest_level(N, degrees, rule, prec):
         _, info64 = H64.solve(b, rtol=1e-8, check_every=1)
         assert info["iterations"] <= 2 * info64["iterations"] + 2, (info["iterations"], info64["iterations"])
 
+
+
+def test_pmg_solve_from_initial_guess():
+    """use_x0: a loose solve, then the tight one started from its result (the outer CG corrects x0)."""
+    print("\n[case] pmg warm start N=5 degrees=(4, 2, 1) gll", flush=True)
+    with Hierarchy(5, (4, 2, 1), warp="B") as H:
+        b = _rhs(H)
+        x_full, info_full = H.solve(b, rtol=1e-10, check_every=1)
+        x0, info0 = H.solve(b, rtol=1e-4, check_every=1)
+        x, info = H.solve(b, x=x0.clone(), rtol=1e-10, check_every=1, use_x0=1)
+        assert info["true_rel_residual"] <= 1.05e-10, info
+        assert info["iterations"] < info_full["iterations"], (info["iterations"], info_full["iterations"])
+        assert float(torch.linalg.norm(x - x_full) / torch.linalg.norm(x_full)) <= 1e-8
