@@ -127,6 +127,10 @@ typedef struct {
                            the degree-7 collocated apply scatters together (0: the
                            per-element scatter is used)                          */
   int64_t nstrip_colors; /* strip colors (launches per apply when nstrips > 0)   */
+  int index_mode;       /* element restriction read by the fused kernels: 0 the full
+                           index array; 1 one id per r1-row (every r1-row of every
+                           element holds consecutive ids); 2 three numbers per
+                           element (base + i + j s_j + k s_k for every element)  */
 } hx_mesh_stats;
 
 hx_status hx_mesh_get_stats(hx_mesh mesh, hx_mesh_stats *stats);
@@ -378,12 +382,14 @@ hx_status hx_mlp_train(hx_mlp net, const float *X, const float *T, int64_t nsamp
  *     FP32, caller element order), the inputs for a residual r (FP64 L-vector).
  *   hx_op_mlp_targets: T [nelem][(p+1)^3] (device FP32, caller order): the
  *     training targets D^1/2 err_e / |r~_e| for an error vector err (FP64).
- *   hx_op_mlp_precond: z = the correction for r (device FP64), bf16 matrix cores.
+ *   hx_op_mlp_precond: the map of the HX_PC_MLP solve for r (device FP64; z must
+ *     not alias r), on bf16 matrix cores: mode 0 z = the correction; mode 1
+ *     z = D^-1 r + the correction (D^-1 r is 0 on constrained nodes).
  * Asynchronous. Errors: HX_EINVAL (shapes), HX_EUNSUPPORTED (not scalar
  * diffusion), HX_ENOMEM, HX_EHIP. */
 hx_status hx_op_mlp_features(hx_op op, const double *r, float *X, float *rnorm, hx_stream s);
 hx_status hx_op_mlp_targets(hx_op op, const double *err, const float *rnorm, float *T, hx_stream s);
-hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, const double *r, double *z, hx_stream s);
+hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, int mode, const double *r, double *z, hx_stream s);
 
 /* ------------------------------------------------------------------------ */
 /* p-multigrid                                                               */

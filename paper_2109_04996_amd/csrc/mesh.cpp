@@ -508,6 +508,7 @@ extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
     s->max_color = std::max<int64_t>(s->max_color, m->color_start[c + 1] - m->color_start[c]);
   s->nstrips = m->nstrips;
   s->nstrip_colors = m->nstrip_colors;
+  s->index_mode = m->idx_affine.ptr ? 2 : m->idx_rows.ptr ? 1 : 0;
   return HX_OK;
 }
 

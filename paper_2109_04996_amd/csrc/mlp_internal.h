@@ -26,6 +26,7 @@ hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uin
 // per-operator set-up of the learned preconditioner (node log kappa, element features and scales,
 // partition-of-unity weights); done once, on first use
 hx_status mlp_prepare(hx_op_s &op, hipStream_t s);
-// learned preconditioner z = G^T (w * scale_e * |r_e| * net(features_e(r))), FP64 L-vectors
-hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, const double *r, double *z, hipStream_t s);
+// learned preconditioner z = D^-1/2 G^T (w * |r~_e| * net(features_e(r))), FP64 L-vectors; mode 1 adds the
+// Jacobi step D^-1 r (0 on constrained nodes)
+hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, int mode, const double *r, double *z, hipStream_t s);
 }  // namespace hx

@@ -141,6 +141,13 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// z += D^-1 r on free nodes (the Jacobi step of the mode-1 map)
+__global__ void k_jacobi_add(int64_t n, const double *__restrict__ diag, const uint8_t *__restrict__ fm,
+                             const double *__restrict__ r, double *__restrict__ z) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    if (fm[t]) z[t] += (1.0 / diag[t]) * r[t];
+}
+
 // training features in caller element order (FP32): [r~_e / |r~_e|, feature]; |r~_e|
 __global__ void __launch_bounds__(kThreads)
     k_features_f32(int P, const int32_t *__restrict__ idx, const int32_t *__restrict__ order,
@@ -226,7 +233,8 @@ hx_status mlp_prepare(hx_op_s &op, hipStream_t s) {
   return HX_OK;
 }
 
-hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, const double *r, double *z, hipStream_t s) {
+hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, int mode, const double *r, double *z, hipStream_t s) {
+  if (mode != 0 && mode != 1) return fail(HX_EINVAL, "mode must be 0 (network correction) or 1 (plus D^-1 r)");
   const int P3 = op.P * op.P * op.P;
   if (net.n_in != 2 * P3 || net.n_out != P3)
     return fail(HX_EINVAL, "network shape must be (2 (p+1)^3 inputs, (p+1)^3 outputs) for this operator");
@@ -249,6 +257,8 @@ hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, const double *r, double 
       hipLaunchKernelGGL(k_mlp_scatter, dim3((unsigned)(e1 - e0)), dim3(kThreads), 0, s, op.P, m.idx.ptr, m.own.ptr,
                          op.mlp_y.ptr, op.mlp_rnorm.ptr, op.mlp_dis.ptr, op.mlp_wmult.ptr, z, e0);
   }
+  if (mode == 1)
+    hipLaunchKernelGGL(k_jacobi_add, dim3(2048), dim3(256), 0, s, m.nnodes, op.diag.ptr, m.freemask.ptr, r, z);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -279,7 +289,9 @@ extern "C" hx_status hx_op_mlp_targets(hx_op op, const double *err, const float 
   return HX_OK;
 }
 
-extern "C" hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, const double *r, double *z, hx_stream stream) {
+extern "C" hx_status hx_op_mlp_precond(hx_op op, hx_mlp net, int mode, const double *r, double *z,
+                                       hx_stream stream) {
   if (!op || !net || !r || !z) return fail(HX_EINVAL, "null argument");
-  return mlp_precond_apply(*op, *net, r, z, static_cast<hipStream_t>(stream));
+  if (r == z) return fail(HX_EINVAL, "z must not alias r");
+  return mlp_precond_apply(*op, *net, mode, r, z, static_cast<hipStream_t>(stream));
 }

@@ -281,13 +281,6 @@ __global__ void __launch_bounds__(kVecThreads) k_convert(int64_t n, double scale
     b[t] = (TB)(scale * (double)a[t]);
 }
 
-// z += dinv r (Jacobi step added to a correction already in z)
-__global__ void __launch_bounds__(kVecThreads) k_jac_add(int64_t n, const double *__restrict__ dinv,
-                                                           const double *__restrict__ r, double *__restrict__ z) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    z[i] += dinv[i] * r[i];
-}
-
 // w = m (r - w): masked residual, in place over w = A z (nc interleaved components share a node's mask)
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads) k_mresid(int64_t n, int nc, const T *__restrict__ r,
@@ -940,9 +933,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   }
   // learned maps: mode 1 base M r = D^-1 r + network correction; mode 2 runs Chebyshev steps over it
   PrecFn<double> mlp_base = [&](const double *r, double *z) -> hx_status {
-    if (hx_status st = mlp_precond_apply(*op, *o.mlp, r, z, s)) return st;
-    LAUNCH_V(k_jac_add, n, v.dinv, r, z);
-    return HX_OK;
+    return mlp_precond_apply(*op, *o.mlp, 1, r, z, s);
   };
   Cheb chm;
   chm.degree = o.cheb_degree;
@@ -1010,7 +1001,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       return HX_OK;
     };
     PrecFn<double> pcm = [&](const double *r, double *z) -> hx_status {
-      if (o.mlp_mode == 0) return mlp_precond_apply(*op, *o.mlp, r, z, s);
+      if (o.mlp_mode == 0) return mlp_precond_apply(*op, *o.mlp, 0, r, z, s);
       if (o.mlp_mode == 1) return mlp_base(r, z);
       return cheb_apply_base(c, chm, v, mlp_base, r, z);
     };

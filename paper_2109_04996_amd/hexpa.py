@@ -36,7 +36,7 @@ class HexpaError(RuntimeError):
 class hx_mesh_stats(C.Structure):
     _fields_ = [("p", C.c_int), ("ncolors", C.c_int), ("nelem", C.c_int64), ("nnodes", C.c_int64),
                 ("nfree", C.c_int64), ("nuntouched", C.c_int64), ("max_color", C.c_int64),
-                ("nstrips", C.c_int64), ("nstrip_colors", C.c_int64)]
+                ("nstrips", C.c_int64), ("nstrip_colors", C.c_int64), ("index_mode", C.c_int)]
 
 
 class hx_kappa_rff(C.Structure):
@@ -117,7 +117,7 @@ SIGNATURES = [
     ("hx_mlp_destroy", None, [_VP]),
     ("hx_op_mlp_features", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hx_op_mlp_targets", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
-    ("hx_op_mlp_precond", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("hx_op_mlp_precond", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("hx_pcg_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(hx_solve_opts), C.POINTER(hx_solve_info), _VP]),
     ("hx_pmg_opts_default", None, [C.POINTER(hx_pmg_opts)]),
     ("hx_pmg_create", C.c_int, [_VP, C.c_int, C.POINTER(hx_pmg_opts), _VP, C.POINTER(_VP)]),
@@ -431,5 +431,5 @@ def hx_op_mlp_targets(op, err, rnorm, T, stream=None):
     _check(load().hx_op_mlp_targets(op, _ptr(err), _ptr(rnorm), _ptr(T), _stream(stream)), "hx_op_mlp_targets")
 
 
-def hx_op_mlp_precond(op, net, r, z, stream=None):
-    _check(load().hx_op_mlp_precond(op, net, _ptr(r), _ptr(z), _stream(stream)), "hx_op_mlp_precond")
+def hx_op_mlp_precond(op, net, r, z, mode=0, stream=None):
+    _check(load().hx_op_mlp_precond(op, net, mode, _ptr(r), _ptr(z), _stream(stream)), "hx_op_mlp_precond")

@@ -27,10 +27,14 @@ from the reference cube; here the bricks tile the unit cube):
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 __all__ = [
     "lattice_mesh",
+    "rotate_elements",
+    "renumber_rows",
     "uniform_vector",
     "kappa_field_params",
     "lattice_node_ijk",
@@ -95,6 +99,59 @@ def lattice_mesh(N: int, p: int, warp="A", shuffle_seed=0) -> dict:
     boundary = ((ni == 0) | (ni == M - 1) | (nj == 0) | (nj == M - 1) | (nk == 0) | (nk == M - 1)).astype(np.uint8)
     return dict(verts=verts, elem_verts=elem_verts, elem_nodes=elem_nodes, boundary=boundary,
                 elem_ijk=eijk, N=N, p=p, nnodes=n, nelem=eijk.shape[0])
+
+
+def _rotations():
+    """The 24 proper rotations of the reference cube as (axis permutation, flips)."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inv = sum(1 for i in range(3) for j in range(i + 1, 3) if perm[i] > perm[j])
+        for flips in itertools.product((0, 1), repeat=3):
+            if (-1) ** inv * (-1) ** sum(flips) == 1:
+                out.append((perm, flips))
+    return out
+
+
+def rotate_elements(mesh: dict, p: int, frac: float, seed: int) -> dict:
+    """Renumber the local nodes and corners of a seeded random subset (fraction ``frac``) of the
+    elements by a proper rotation of the reference cube: the same hexahedra and the same assembled
+    operator, with other local orientations (so chains of face-adjacent elements break and no
+    element-wise affine numbering exists)."""
+    P = p + 1
+    rng = np.random.default_rng(seed)
+    E = mesh["nelem"]
+    en = mesh["elem_nodes"].reshape(E, P, P, P).copy()  # [e][k][j][i]
+    ev = mesh["elem_verts"].reshape(E, 2, 2, 2).copy()  # [e][c][b][a]
+    rots = [r for r in _rotations() if r != ((0, 1, 2), (0, 0, 0))]
+    for e in np.flatnonzero(rng.random(E) < frac):
+        perm, flips = rots[rng.integers(len(rots))]
+        for arr in (en, ev):
+            a = np.transpose(arr[e].transpose(2, 1, 0), perm)  # axes (r1, r2, r3), permuted
+            for d in range(3):
+                if flips[d]:
+                    a = np.flip(a, axis=d)
+            arr[e] = a.transpose(2, 1, 0)
+    out = dict(mesh)
+    out["elem_nodes"] = np.ascontiguousarray(en.reshape(E, P ** 3))
+    out["elem_verts"] = np.ascontiguousarray(ev.reshape(E, 8))
+    return out
+
+
+def renumber_rows(mesh: dict, seed: int) -> dict:
+    """Relabel the L-nodes of a lattice mesh by a seeded permutation of whole x-rows of the node
+    lattice: node ``i + M r`` (row ``r = j + M k``) becomes ``i + M perm[r]``. Every element's rows
+    along its first local axis keep consecutive ids, but no element-wise affine numbering is left.
+    ``boundary`` moves with the nodes; ``verts`` and ``elem_verts`` are unchanged."""
+    M = mesh["N"] * mesh["p"] + 1
+    perm = np.random.default_rng(seed).permutation(M * M)
+    old = np.arange(M ** 3)
+    new = perm[old // M] * M + old % M
+    out = dict(mesh)
+    out["elem_nodes"] = new[mesh["elem_nodes"]].astype(np.int32)
+    bnd = np.empty_like(mesh["boundary"])
+    bnd[new] = mesh["boundary"]
+    out["boundary"] = bnd
+    return out
 
 
 def lattice_node_ijk(N: int, p: int) -> np.ndarray:

@@ -13,7 +13,7 @@ from oracle import fem  # noqa: E402
 from oracle import mlp as omlp  # noqa: E402
 from paper_2109_04996_amd import hexpa as hx  # noqa: E402
 from paper_2109_04996_amd import learned  # noqa: E402
-from paper_2109_04996_amd.inputs import kappa_field_params, lattice_mesh  # noqa: E402
+from paper_2109_04996_amd.inputs import kappa_field_params, lattice_mesh, rotate_elements  # noqa: E402
 from paper_2109_04996_amd.problem import Problem  # noqa: E402
 
 
@@ -161,6 +161,37 @@ def test_learned_fcg_solve_and_gain(trained):
         assert lr["iterations"] <= res["jacobi"]["iterations"] + 40 or lr["fallback_used"] == 1
 
 
+def _anorm_reduction(pr, e, z, r):
+    """|e - a z|_A / |e|_A at the best step a = z'r / z'Az (r = A e): the error reduction of one
+    application of the map that gave z."""
+    Az = pr.apply(z) * pr.to_dev((pr.mesh["boundary"] == 0).astype(np.float64))
+    eAe = float(torch.dot(e, r))
+    zr, zAz = float(torch.dot(z, r)), float(torch.dot(z, Az))
+    return float(np.sqrt(max(0.0, 1.0 - zr * zr / (zAz * eAe))))
+
+
+def test_learned_map_gain_per_application(trained):
+    # What the trained network adds, measured on a held-out coefficient field (seed 100): the A-norm
+    # error reduction of one application of the learned map (mode 1: D^-1 r plus the network's
+    # correction) against one Jacobi step D^-1 r, at the best step length, for rough errors (seeded
+    # uniform on the free nodes, the element-scale content an element-local map can act on).
+    net, _ = trained
+    pr, b = learned.problem_with_kappa(6, 3, 5, "gauss", 100, kappa_M=128)
+    with pr:
+        fm = pr.to_dev((pr.mesh["boundary"] == 0).astype(np.float64))
+        dinv = fm / pr.diagonal()
+        out = []
+        for seed in (21, 22, 23):
+            e = pr.to_dev(np.random.default_rng(seed).uniform(-1.0, 1.0, pr.n)) * fm
+            r = pr.apply(e) * fm
+            zl = pr.zeros()
+            hx.hx_op_mlp_precond(pr.h_op, net, r, zl, mode=1)
+            out.append((_anorm_reduction(pr, e, zl, r), _anorm_reduction(pr, e, dinv * r, r)))
+        print("\n[learned] A-norm reduction per application (learned, jacobi):", out, flush=True)
+        for rl, rj in out:
+            assert rl < rj, out
+
+
 def test_fallback_on_broken_network(trained):
     net, _ = trained
     pr, b = learned.problem_with_kappa(5, 3, 5, "gauss", 101, kappa_M=128)
@@ -186,3 +217,53 @@ def test_fallback_on_broken_network(trained):
             assert info["fallback_used"] == 1 and info["status"] == "HX_OK", info
         finally:
             hx.hx_mlp_destroy(bad)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_learned_map_matches_oracle_composition(mode):
+    # hx_op_mlp_precond against its definition composed on the CPU from the oracle: the assembled
+    # diagonal D, kappa at the oracle's node coordinates, the FP64 network forward of the library's FP32
+    # parameters, the 1/multiplicity weights of elem_nodes and the D^-1/2 scalings:
+    #   z = D^-1/2 sum_e G_e^T (w |r~_e| net([r~_e/|r~_e|, f_e]))  (+ D^-1 r in mode 1),  r~ = D^-1/2 r.
+    # Mesh B with 15% of the elements rotated (shared and constrained nodes in every orientation).
+    # Bound: the network runs on bf16 matrix cores (operands rounded to 2^-9, bf16 hidden activations),
+    # 2e-2 of the forward's scale as in the bf16 forward test, node by node against the sum of the
+    # magnitudes of the node's element contributions.
+    p, N, q = 3, 4, 5
+    P3 = (p + 1) ** 3
+    print(f"\n[case] learned map mode={mode}", flush=True)
+    kp = kappa_field_params(1002, M=64)
+    mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=3), p, 0.15, seed=4)
+    A = fem.assemble(mesh, p, q, "gauss", "diffusion", kappa=kp)
+    free = mesh["boundary"] == 0
+    d = fem.diagonal(A)
+    dis = np.where(free, 1.0 / np.sqrt(d), 0.0)
+    EN = mesh["elem_nodes"].astype(np.int64)
+    r = np.random.default_rng(8).standard_normal(mesh["nnodes"])  # constrained entries must be ignored
+    net = hx.hx_mlp_create(2 * P3, 128, P3, 5)
+    try:
+        prm = hx.hx_mlp_get_params(net)
+        prm[:] = np.random.default_rng(9).uniform(-0.2, 0.2, prm.size).astype(np.float32)
+        hx.hx_mlp_set_params(net, prm)
+        with Problem(N, p, q, "gauss", "diffusion", mesh=mesh, kappa=kp) as pr:
+            z = torch.full((mesh["nnodes"],), 7.0, dtype=torch.float64, device="cuda")  # overwritten
+            hx.hx_op_mlp_precond(pr.h_op, net, pr.to_dev(r), z, mode=mode)
+            z = z.cpu().numpy()
+        re = (dis * r)[EN]
+        nrm = np.linalg.norm(re, axis=1)
+        lk = np.log(fem.kappa_eval(kp, fem.node_coordinates(mesh, p)))[EN]
+        feat = np.where(free[EN], lk - lk.mean(axis=1, keepdims=True), 3.0)
+        Y, _ = omlp.forward(_split(prm, 2 * P3, 128, P3), np.hstack([re / nrm[:, None], feat]))
+        w = np.where(free, 1.0 / np.bincount(EN.ravel(), minlength=mesh["nnodes"]), 0.0)
+        zo = np.zeros(mesh["nnodes"])
+        np.add.at(zo, EN, nrm[:, None] * Y)
+        scale = np.zeros(mesh["nnodes"])
+        np.add.at(scale, EN, nrm[:, None] * np.abs(Y))
+        zo, scale = dis * w * zo, dis * w * scale
+        if mode == 1:
+            zo = zo + np.where(free, r / d, 0.0)
+        assert np.all(z[~free] == 0.0)
+        assert np.all(np.abs(z - zo) <= 2e-2 * scale + 1e-14 * np.abs(zo)), np.abs(z - zo).max()
+        assert np.linalg.norm(z - zo) <= 2e-2 * np.linalg.norm(zo)
+    finally:
+        hx.hx_mlp_destroy(net)

@@ -16,9 +16,8 @@ pytestmark = pytest.mark.gpu
 
 from oracle import fem, pmg, solvers  # noqa: E402
 from paper_2109_04996_amd import hexpa as hx  # noqa: E402
-from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector  # noqa: E402
+from paper_2109_04996_amd.inputs import lattice_mesh, rotate_elements, uniform_vector  # noqa: E402
 from paper_2109_04996_amd.problem import Hierarchy  # noqa: E402
-from test_gpu_strips import rotate_elements  # noqa: E402
 
 
 def rel(a, b):

@@ -1,5 +1,6 @@
 """GPU PCG solves against the oracle: iteration counts, residuals, and solutions vs a direct solve."""
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -143,3 +144,30 @@ def test_graph_replay_matches_eager(form):
         assert i0["operator_applies"] == i1["operator_applies"]
         assert torch.equal(x0, x1) and torch.equal(x1, x2)
         assert i1["true_rel_residual"] <= 1.05e-8
+
+
+@pytest.mark.parametrize("cheb_prec,tol", [(hx.HX_FP64, 1e-12), (hx.HX_FP32, 3e-5), (hx.HX_BF16_SPLIT, 1.2e-2),
+                                           (hx.HX_BF16, 6e-2)])
+def test_chebyshev_action_matches_oracle(cheb_prec, tol):
+    # The preconditioner's action itself: one CG iteration from x = 0 leaves x = alpha M b (p_0 = z_0 =
+    # M b), so x / |x| is the direction of the Chebyshev action M b. It is compared with the oracle's
+    # recurrence (degree 4, the masked operator) on the interval the library used: lam_hi = 1.1 lam_max
+    # with the library's estimate, lam_lo = lam_hi / 30. Bounds: FP64 round-off; FP32 and bf16 three
+    # times the single-apply bounds of the FP32 and bf16 parity tests (degree 4 = three operator applies
+    # whose terms are of the size of the result).
+    mesh, pr, b, A, bo, free = _setup(4, 4, 6, "gauss", warp="B")
+    with pr:
+        x, info = pr.solve(b, rtol=1e-30, maxit=1, check_every=1, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=cheb_prec,
+                           raise_on_error=False)
+        assert info["status"] == "HX_ENOCONV" and info["iterations"] == 1, info
+        lam = info["lam_max"]
+        lmax = solvers.jacobi_lambda_max(A, free)
+        assert 0.8 * lmax <= lam <= 1.0001 * lmax
+        f = free.astype(float)
+        Am = sp.diags(f) @ A @ sp.diags(f)
+        dinv = np.where(free, 1.0 / A.diagonal(), 0.0)
+        z = solvers.chebyshev_apply(Am, dinv, bo * f, 1.1 * lam / 30.0, 1.1 * lam, 4)
+        xv = x.cpu().numpy()
+        d = xv / np.linalg.norm(xv) - z / np.linalg.norm(z)
+        assert np.linalg.norm(d) <= tol, np.linalg.norm(d)
+        assert np.all(xv[~free] == 0)

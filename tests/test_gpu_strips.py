@@ -5,8 +5,6 @@ against the FP64 oracle on meshes whose elements have random proper rotations (s
 and strips of every length from 1 to 8 occur), and at the full benchmark size against the
 E-vector path (element kernel, no scatter) summed node by node.
 """
-import itertools
-
 import numpy as np
 import pytest
 
@@ -15,46 +13,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle import fem  # noqa: E402
-from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector  # noqa: E402
+from paper_2109_04996_amd.inputs import lattice_mesh, rotate_elements, uniform_vector  # noqa: E402
 from paper_2109_04996_amd.problem import Problem  # noqa: E402
 
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def _rotations():
-    """The 24 proper rotations of the reference cube as (axis permutation, flips)."""
-    out = []
-    for perm in itertools.permutations(range(3)):
-        inv = sum(1 for i in range(3) for j in range(i + 1, 3) if perm[i] > perm[j])
-        for flips in itertools.product((0, 1), repeat=3):
-            if (-1) ** inv * (-1) ** sum(flips) == 1:
-                out.append((perm, flips))
-    return out
-
-
-def rotate_elements(mesh, p, frac, seed):
-    """Renumber the local nodes and corners of a random subset of elements by a proper rotation:
-    the same hexahedra and the same assembled operator, with other local orientations."""
-    P = p + 1
-    rng = np.random.default_rng(seed)
-    E = mesh["nelem"]
-    en = mesh["elem_nodes"].reshape(E, P, P, P).copy()  # [e][k][j][i]
-    ev = mesh["elem_verts"].reshape(E, 2, 2, 2).copy()  # [e][c][b][a]
-    rots = [r for r in _rotations() if r != ((0, 1, 2), (0, 0, 0))]
-    for e in np.flatnonzero(rng.random(E) < frac):
-        perm, flips = rots[rng.integers(len(rots))]
-        for arr in (en, ev):
-            a = np.transpose(arr[e].transpose(2, 1, 0), perm)  # axes (r1, r2, r3), permuted
-            for d in range(3):
-                if flips[d]:
-                    a = np.flip(a, axis=d)
-            arr[e] = a.transpose(2, 1, 0)
-    out = dict(mesh)
-    out["elem_nodes"] = np.ascontiguousarray(en.reshape(E, P ** 3))
-    out["elem_verts"] = np.ascontiguousarray(ev.reshape(E, 8))
-    return out
 
 
 @pytest.mark.parametrize("p,N,nstrips", [(7, 4, 16), (4, 4, 16), (2, 4, 16), (3, 4, 16), (6, 4, 16), (4, 9, 162),

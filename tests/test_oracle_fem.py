@@ -252,3 +252,27 @@ def test_kappa_field_contrast():
     A1 = fem.assemble(mesh, 2, 4, "gauss", "diffusion")
     A2 = fem.assemble(mesh, 2, 4, "gauss", "diffusion", kappa=dict(kp, scale=0.0, shift=np.log(2.0)))
     assert abs(A2 - 2 * A1).max() < 1e-14 * abs(A1).max()
+
+
+@pytest.mark.parametrize("N,p,q,tol", [(4, 5, 7, 1e-12), (4, 3, 5, 1e-9)])
+def test_kappa_location_closed_form(N, p, q, tol):
+    # where kappa is evaluated: a coefficient that varies along x alone (one feature, omega = (w, 0, 0),
+    # phase -pi/2, so g = sqrt(2) sin(w x)). On mesh A (axis-aligned bricks) the coordinate functions
+    # and their squares lie in V_h, so for u in {y, x^2, y^2}
+    #   u^T A u = int kappa |grad u|^2 = int_0^1 kappa(x) dx, 4 int_0^1 kappa(x) x^2 dx, (4/3) int_0^1 kappa(x) dx,
+    # up to the element rule's quadrature error. The 1D integrals come from a 200-point Gauss rule on
+    # [0, 1] that does not use the mesh. Evaluating kappa at reference coordinates, at another axis or
+    # at the element's nodes instead of its physical quadrature points breaks one of the three.
+    w, sc, sh = 3.0, 0.5, 0.1
+    kp = dict(omega=np.array([[w, 0.0, 0.0]]), phase=np.array([-np.pi / 2]), scale=sc, shift=sh, M=1)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=2)
+    A = fem.assemble(mesh, p, q, "gauss", "diffusion", kappa=kp)
+    X = fem.node_coordinates(mesh, p)
+    t, wt = np.polynomial.legendre.leggauss(200)
+    t, wt = 0.5 * (t + 1.0), 0.5 * wt
+    kap = np.exp(sc * np.sqrt(2.0) * np.sin(w * t) + sh)
+    I0, I2 = float(wt @ kap), float(wt @ (kap * t * t))
+    y, x2, y2 = X[:, 1], X[:, 0] ** 2, X[:, 1] ** 2
+    assert abs(y @ (A @ y) / I0 - 1.0) <= tol
+    assert abs(x2 @ (A @ x2) / (4.0 * I2) - 1.0) <= tol
+    assert abs(y2 @ (A @ y2) / (4.0 / 3.0 * I0) - 1.0) <= tol

@@ -25,6 +25,11 @@ MUTANTS = {
     "cofactor_sign": ("fem.py", "cof[:, 1, 2] = -(a[:, 0, 0]", "cof[:, 1, 2] = (a[:, 0, 0]"),
     "swapped_derivative_tables": ("fem.py", "outer(phi, dphi, phi), outer(dphi, phi, phi)",
                                   "outer(dphi, phi, phi), outer(phi, dphi, phi)"),
+    "kappa_at_reference_points": ("fem.py", "wd = er.w3 * det * kappa_eval(kappa, x)",
+                                  "wd = er.w3 * det * kappa_eval(kappa, er.r3)"),
+    "kappa_axes_swapped": ("fem.py", "wd = er.w3 * det * kappa_eval(kappa, x)",
+                           "wd = er.w3 * det * kappa_eval(kappa, x[:, ::-1])"),
+    "lambda_max_unscaled": ("solvers.py", "S = sp.diags(s) @ Aii @ sp.diags(s)", "S = Aii"),
     "gll_weight_formula": ("quadrature.py", "w = 2.0 / (p * (p + 1) * Pp * Pp)", "w = 2.0 / (p * (p + 1) * Pp)"),
     "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * res)",
                               "d = rho_new * d + (2.0 * rho_new / delta) * (dinv * res)"),
@@ -36,9 +41,11 @@ MUTANTS = {
 
 PINS = {
     "fem.py": ("test_oracle_fem", ["test_mass_integrates_volume", "test_coordinate_function_forms",
-                                   "test_diffusion_invariants", "test_collocated_diagonal_closed_form"]),
+                                   "test_diffusion_invariants", "test_collocated_diagonal_closed_form",
+                                   "test_kappa_location_closed_form"]),
     "quadrature.py": ("test_oracle_quadrature", ["test_closed_forms", "test_exactness_degrees"]),
-    "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial"]),
+    "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial",
+                                           "test_lambda_max_lanczos_branch"]),
     "pmg.py": ("test_oracle_pmg", ["test_interpolation_1d", "test_prolongation_reproduces_coarse_space",
                                    "test_galerkin_identity", "test_vcycle_symmetric_and_contracting"]),
 }

@@ -84,6 +84,17 @@ def test_lambda_max_dense():
     assert abs(solvers.jacobi_lambda_max(A, free) - ev.real.max()) < 1e-10
 
 
+def test_lambda_max_lanczos_branch():
+    # more than 64 free nodes (N = 3, p = 2: 125): the sparse Lanczos branch, against the dense
+    # eigenvalues of the non-symmetric D^-1 A_II computed without the symmetric scaling
+    mesh, A, b, free = _problem(N=3, p=2)
+    assert int(free.sum()) > 64
+    Aii = A[free][:, free].toarray()
+    ev = np.linalg.eigvals(Aii / np.diag(Aii)[:, None])
+    assert abs(ev.imag).max() < 1e-10
+    assert abs(solvers.jacobi_lambda_max(A, free) - ev.real.max()) < 1e-9 * ev.real.max()
+
+
 def test_mlp_gradients_finite_differences():
     rng = np.random.default_rng(0)
     params = mlp.init_params(10, 7, 4, seed=7)
