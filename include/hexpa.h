@@ -60,7 +60,8 @@ enum {
 };
 
 enum { HX_GAUSS = 0, HX_GLL = 1 };          /* quadrature rule families               */
-enum { HX_MASS = 0, HX_DIFFUSION = 1 };      /* B and A of the bake-off problems       */
+enum { HX_MASS = 0, HX_DIFFUSION = 1,       /* B and A of the bake-off problems       */
+       HX_HELMHOLTZ = 2 };                   /* alpha A + beta B (hx_op_create_helmholtz) */
 /* Arithmetic precisions. HX_BF16: matrix-core products of operands rounded to
  * bfloat16, accumulated in FP32. HX_BF16_SPLIT: the same matrix cores with every
  * operand carried as hi + lo, both bfloat16 (lo the rounding error of hi), and the
@@ -188,6 +189,21 @@ typedef struct {
 hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const hx_kappa_rff *kappa,
                        hx_stream s, hx_op *out);
 
+/* Create the Helmholtz operator alpha A + beta B of the bake-off problems
+ * (Benchmarks section: the systems are (alpha A + beta B) u = B f; A the
+ * diffusion operator with the optional coefficient kappa, B the mass operator,
+ * both integrated with the basis's rule). Kind HX_HELMHOLTZ: stored as alpha
+ * times the diffusion factors (6 values per point) plus beta * w * detJ (1 value
+ * per point), computed in FP64 on the GPU in one pass; every apply evaluates
+ * both terms in one fused kernel (on the GLL-collocated rule the mass term is
+ * diagonal). Every entry point that takes an operator accepts it, except the
+ * bf16 matrix-core apply and the learned preconditioner (HX_EUNSUPPORTED).
+ *   alpha, beta  finite, >= 0, not both 0 (alpha = 0: the mass operator on the
+ *                diffusion code path; beta = 0: the diffusion operator)
+ * Errors: as hx_op_create; HX_EINVAL for alpha or beta out of range. */
+hx_status hx_op_create_helmholtz(hx_mesh mesh, hx_basis basis, int ncomp, double alpha, double beta,
+                                 const hx_kappa_rff *kappa, hx_stream s, hx_op *out);
+
 /* y = A x on the whole L-vector (no boundary condition), FP64.
  * x, y: device, nnodes*ncomp doubles. y is overwritten. Asynchronous.
  * Deterministic: the same x gives bit-identical y on every call.
@@ -283,7 +299,22 @@ typedef struct {
                           kernel on the caller's stream                         */
   hx_pmg pmg;          /* HX_PC_PMG: the hierarchy, whose finest operator is the
                           solved one; one V-cycle per iteration, flexible CG    */
+  int scatter;         /* the FP64 operator of the CG iteration itself:
+                          HX_SCATTER_COLORS: the colored atomic-free scatter (one
+                          launch per element or strip color);
+                          HX_SCATTER_GATHER: the element kernel writes the E-vector
+                          in one launch and a node gather (the transpose of the
+                          element restriction, each node's contributions summed in a
+                          fixed order) forms A p with p'Ap fused: two launches, for
+                          small problems where each launch's fixed cost dominates;
+                          the E-vector (nelem*ncomp*(p+1)^3 doubles) and the
+                          transpose (nelem*(p+1)^3 + nnodes + 1 ints) are kept by the
+                          operator and its mesh. Results differ from
+                          HX_SCATTER_COLORS in the last bits (summation order) and
+                          are deterministic                                        */
 } hx_solve_opts;
+
+enum { HX_SCATTER_COLORS = 0, HX_SCATTER_GATHER = 1 };
 
 typedef struct {
   int iterations;        /* PCG iterations (sum of inner iterations for IR)  */
@@ -307,7 +338,7 @@ typedef struct {
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
  * inner_rtol 1e-4, inner_maxit 10000, FP64 inner qdata, flexible 0, no network,
  * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1,
- * graph 0, no hierarchy. */
+ * graph 0, no hierarchy, HX_SCATTER_COLORS. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:

@@ -164,6 +164,15 @@ def assemble(mesh: dict, p: int, q: int, rule: str, kind: str, kappa=None) -> sp
     return A
 
 
+def assemble_helmholtz(mesh: dict, p: int, q: int, rule: str, alpha: float, beta: float,
+                       kappa=None) -> sp.csr_matrix:
+    """alpha A + beta B, both assembled with the same rule (Benchmarks section: the bake-off systems
+    are (alpha A + beta B) u = B f)."""
+    A = assemble(mesh, p, q, rule, "diffusion", kappa)
+    B = assemble(mesh, p, q, rule, "mass")
+    return (alpha * A + beta * B).tocsr()
+
+
 def apply(A: sp.csr_matrix, x: np.ndarray, ncomp: int = 1) -> np.ndarray:
     """y = A x on an L-vector; for ncomp = 3 the scalar A acts on each interleaved component."""
     if ncomp == 1:

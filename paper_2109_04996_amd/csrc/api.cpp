@@ -1,4 +1,5 @@
 // C ABI: error reporting, bases, operators and applies.
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -79,12 +80,13 @@ extern "C" hx_status hx_basis_get_tables(hx_basis basis, double *nodes, double *
 extern "C" void hx_basis_destroy(hx_basis basis) { delete basis; }
 
 // ------------------------------------------------------------------ operators
-extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const hx_kappa_rff *kappa,
-                                  hx_stream stream, hx_op *out) {
+namespace {
+
+hx_status op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, double alpha, double beta,
+                    const hx_kappa_rff *kappa, hx_stream stream, hx_op *out) {
   if (!out) return fail(HX_EINVAL, "out is null");
   *out = nullptr;
   if (!mesh || !basis) return fail(HX_EINVAL, "null mesh or basis");
-  if (kind != HX_MASS && kind != HX_DIFFUSION) return fail(HX_EINVAL, "kind must be HX_MASS or HX_DIFFUSION");
   if (ncomp != 1 && ncomp != 3) return fail(HX_EINVAL, "ncomp must be 1 or 3");
   if (basis->b.p != mesh->p) return fail(HX_EUNSUPPORTED, "basis degree differs from the mesh degree");
   if (kappa && kind == HX_MASS) return fail(HX_EINVAL, "a coefficient applies to HX_DIFFUSION only");
@@ -106,8 +108,10 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
   op->ncomp = ncomp;
   op->P = op->b.P;
   op->Q = op->b.q;
-  op->colloc = (kind == HX_DIFFUSION && op->b.rule == HX_GLL && op->Q == op->P);
+  op->colloc = (kind != HX_MASS && op->b.rule == HX_GLL && op->Q == op->P);
   op->ncq = kind == HX_MASS ? 1 : 6;
+  op->alpha = alpha;
+  op->beta = beta;
   const int64_t Q3 = (int64_t)op->Q * op->Q * op->Q;
 
   // device tables: collocated D [P][P]; otherwise interp [Q][P] then the q-point derivative [Q][Q]
@@ -166,7 +170,8 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
   hipError_t e;
   if ((e = op->tab.upload(tab.data(), tab.size())) != hipSuccess ||
       (e = op->tab32.upload(tab32.data(), tab32.size())) != hipSuccess ||
-      (e = op->qdata.alloc((size_t)mesh->nelem * op->ncq * Q3)) != hipSuccess) {
+      (e = op->qdata.alloc((size_t)mesh->nelem * op->ncq * Q3)) != hipSuccess ||
+      (kind == HX_HELMHOLTZ && (e = op->qmass.alloc((size_t)mesh->nelem * Q3)) != hipSuccess)) {
     delete op;
     return hip_fail(e, "operator allocation");
   }
@@ -188,6 +193,26 @@ extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int nc
   }
   *out = op;
   return HX_OK;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const hx_kappa_rff *kappa,
+                                  hx_stream stream, hx_op *out) {
+  if (kind != HX_MASS && kind != HX_DIFFUSION) {
+    if (out) *out = nullptr;
+    return fail(HX_EINVAL, "kind must be HX_MASS or HX_DIFFUSION (hx_op_create_helmholtz makes HX_HELMHOLTZ)");
+  }
+  return op_create(mesh, basis, kind, ncomp, 1.0, 0.0, kappa, stream, out);
+}
+
+extern "C" hx_status hx_op_create_helmholtz(hx_mesh mesh, hx_basis basis, int ncomp, double alpha, double beta,
+                                            const hx_kappa_rff *kappa, hx_stream stream, hx_op *out) {
+  if (!(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0.0 && beta >= 0.0 && alpha + beta > 0.0)) {
+    if (out) *out = nullptr;
+    return fail(HX_EINVAL, "alpha and beta must be finite, >= 0 and not both 0");
+  }
+  return op_create(mesh, basis, HX_HELMHOLTZ, ncomp, alpha, beta, kappa, stream, out);
 }
 
 extern "C" hx_status hx_op_apply(hx_op op, const double *x, double *y, hx_stream s) {

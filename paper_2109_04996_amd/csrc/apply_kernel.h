@@ -26,6 +26,9 @@
 // G11 G12 G13 G22 G23 G33 of w*kappa*detJ*J^-1 J^-T. Layout [e][qc][m][qb][qa]:
 // plane by plane along r3, the components of a plane next to each other, so a
 // wavefront reads each component of a plane as one contiguous run.
+// HELM (the Helmholtz operator alpha A + beta B of the bake-off problems): the
+// diffusion kinds also read qm [e][qc][qb][qa], beta * w * detJ, and add the
+// mass term qm * u at each point to the field that the transposed basis sums.
 //
 // Scatter: no atomics. Elements of one launch never share a node (coloring);
 // bit k of own[e][j][i] says element e is the first to write node (i,j,k),
@@ -74,11 +77,12 @@ __device__ __forceinline__ T ld_q(const TQ *p) {
     return static_cast<T>(__builtin_nontemporal_load(p));
 }
 
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT, bool HELM = false>
 __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_waves_per_eu(2)))
     k_apply(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
-            const int32_t *__restrict__ order, int64_t e_begin, int64_t e_end) {
+            const int32_t *__restrict__ order, int64_t e_begin, int64_t e_end, const TQ *__restrict__ qm = nullptr) {
+  static_assert(!HELM || MODE != MODE_MASS, "the Helmholtz mass term rides on a diffusion kind");
   constexpr int EPB = EpbOf<Q>::v;
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
   constexpr int NCQ = (MODE == MODE_MASS) ? 1 : 6;
@@ -111,6 +115,7 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
     ob = own[e * P2 + b * P + a];
   }
   const TQ *qe = qd + e * (int64_t)(NCQ * Q3) + b * Q + a;
+  const TQ *qme = HELM ? qm + e * (int64_t)Q3 + b * Q + a : nullptr;
   __syncthreads();
 
   {
@@ -145,6 +150,7 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
           const T vt = g2 * ur + g4 * us + g5 * ut;
 #pragma unroll
           for (int m = 0; m < P; ++m) yv[m] += tD[k * P + m] * vt;
+          if constexpr (HELM) yv[k] += ld_q<NC, TQ, T>(qme + k * Q2) * u[k];  // collocated mass: diagonal
         }
       }
       __syncthreads();
@@ -225,6 +231,7 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
             const T vt = g2 * ur + g4 * us + g5 * ut;
 #pragma unroll
             for (int m = 0; m < Q; ++m) w[m] += tD[cq * Q + m] * vt;
+            if constexpr (HELM) w[cq] += ld_q<NC, TQ, T>(qme + cq * Q2) * uq[cq];  // mass term at the point
           }
         }
         __syncthreads();

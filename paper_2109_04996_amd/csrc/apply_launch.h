@@ -11,8 +11,11 @@
 
 namespace hx {
 
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT>
-hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s) {
+// HELM: the Helmholtz operator alpha A + beta B (qd holds alpha times the diffusion factors, qm the
+// mass factors beta w detJ at the points); the diffusion kernels add the mass term in the same pass.
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT, bool HELM = false>
+hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s,
+                        const TQ *qm = nullptr) {
   // strips (one workgroup per strip and component)
   if constexpr (MODE == MODE_COLLOC && colloc_strips(P) && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
@@ -26,14 +29,16 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
         if (s1 <= s0) continue;
         const dim3 grid((unsigned)((s1 - s0) * NC)), block(StripCfg<P>::NW * 64);
         if (m.idx_affine.ptr)
-          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr, qd,
-                             tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2, HELM>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero,
+                             qm);
         else if (m.idx_rows.ptr)
-          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 1>), grid, block, 0, s, m.idx_rows.ptr, m.strip_own.ptr, qd,
-                             tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 1, HELM>), grid, block, 0, s, m.idx_rows.ptr, m.strip_own.ptr,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero,
+                             qm);
         else
-          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 0>), grid, block, 0, s, a.idx, m.strip_own.ptr, qd, tab,
-                             static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero);
+          hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 0, HELM>), grid, block, 0, s, a.idx, m.strip_own.ptr, qd, tab,
+                             static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero, qm);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "k_colloc_strip launch");
@@ -45,18 +50,20 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     using CF = CollocCfg<P>;
     const hx_mesh_s &m = *op.mesh;
     const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
-    for (int c = 0; c < m.ncolors; ++c) {
-      const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
+    // E-vector output writes no shared node: one launch over all elements
+    const int ncol = EOUT ? 1 : m.ncolors;
+    for (int c = 0; c < ncol; ++c) {
+      const int64_t e0 = EOUT ? 0 : m.color_start[c], e1 = EOUT ? m.nelem : m.color_start[c + 1];
       if (e1 <= e0) continue;
       const int64_t nb = (e1 - e0 + CF::EPB - 1) / CF::EPB * NC;  // blocks: element groups x components
       if (m.idx_rows.ptr)
-        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, true>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
+        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, true, HELM>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
                            m.idx_rows.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                           a.order, e0, e1, zero);
+                           a.order, e0, e1, zero, qm);
       else
-        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, false>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
+        hipLaunchKernelGGL((k_colloc<P, NC, T, TQ, EOUT, false, HELM>), dim3((unsigned)nb), dim3(CF::THREADS), 0, s,
                            a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0,
-                           e1, zero);
+                           e1, zero, qm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_colloc launch");
@@ -78,17 +85,17 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
         if (s1 <= s0) continue;
         const dim3 grid((unsigned)((s1 - s0) * NC));
         if (m.idx_affine.ptr)
-          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 2>), grid, block, 0, s, m.idx_affine.ptr,
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 2, HELM>), grid, block, 0, s, m.idx_affine.ptr,
                              m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                             m.strip_elems.ptr, s0, zero);
+                             m.strip_elems.ptr, s0, zero, qm);
         else if (m.idx_rows.ptr)
-          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 1>), grid, block, 0, s, m.idx_rows.ptr,
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 1, HELM>), grid, block, 0, s, m.idx_rows.ptr,
                              m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                             m.strip_elems.ptr, s0, zero);
+                             m.strip_elems.ptr, s0, zero, qm);
         else
-          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 0>), grid, block, 0, s, a.idx, m.strip_own.ptr,
+          hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 0, HELM>), grid, block, 0, s, a.idx, m.strip_own.ptr,
                              qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0,
-                             zero);
+                             zero, qm);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "k_gauss_strip launch");
@@ -101,9 +108,9 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
-      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ>), dim3((unsigned)((e1 - e0) * NC)), dim3(GaussCfg<Q>::NT), 0, s,
-                         a.idx, a.own, qd,
-                         tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero);
+      hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, HELM>), dim3((unsigned)((e1 - e0) * NC)), dim3(GaussCfg<Q>::NT),
+                         0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero,
+                         qm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_gauss launch");
@@ -111,33 +118,46 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   }
   constexpr int EPB = EpbOf<Q>::v;
   const hx_mesh_s &m = *op.mesh;
-  for (int c = 0; c < m.ncolors; ++c) {
-    const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
+  const int ncol = EOUT ? 1 : m.ncolors;  // E-vector output: one launch over all elements
+  for (int c = 0; c < ncol; ++c) {
+    const int64_t e0 = EOUT ? 0 : m.color_start[c], e1 = EOUT ? m.nelem : m.color_start[c + 1];
     if (e1 <= e0) continue;
     const int64_t nb = (e1 - e0 + EPB - 1) / EPB * NC;  // blocks: element groups x components
-    hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s, a.idx,
-                       a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1);
+    hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT, HELM>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s, a.idx,
+                       a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1, qm);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_apply launch");
   return HX_OK;
 }
 
-template <int P, int Q, int MODE, int NC>
-hx_status launch_prec(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
+template <int P, int Q, int MODE, int NC, bool HELM>
+hx_status launch_prec_h(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
   if (eout) {
     if (prec != Prec::F64) return fail(HX_EUNSUPPORTED, "E-vector output is FP64 only");
-    return launch_colors<P, Q, MODE, NC, double, double, true>(op, op.tab.ptr, op.qdata.ptr, a, s);
+    return launch_colors<P, Q, MODE, NC, double, double, true, HELM>(op, op.tab.ptr, op.qdata.ptr, a, s,
+                                                                     op.qmass.ptr);
   }
   switch (prec) {
     case Prec::F64:
-      return launch_colors<P, Q, MODE, NC, double, double, false>(op, op.tab.ptr, op.qdata.ptr, a, s);
+      return launch_colors<P, Q, MODE, NC, double, double, false, HELM>(op, op.tab.ptr, op.qdata.ptr, a, s,
+                                                                        op.qmass.ptr);
     case Prec::F32_Q64:
-      return launch_colors<P, Q, MODE, NC, float, double, false>(op, op.tab32.ptr, op.qdata.ptr, a, s);
+      return launch_colors<P, Q, MODE, NC, float, double, false, HELM>(op, op.tab32.ptr, op.qdata.ptr, a, s,
+                                                                       op.qmass.ptr);
     case Prec::F32_Q32:
-      return launch_colors<P, Q, MODE, NC, float, float, false>(op, op.tab32.ptr, op.qdata32.ptr, a, s);
+      return launch_colors<P, Q, MODE, NC, float, float, false, HELM>(op, op.tab32.ptr, op.qdata32.ptr, a, s,
+                                                                      op.qmass32.ptr);
   }
   return fail(HX_EINVAL, "bad precision");
+}
+
+template <int P, int Q, int MODE, int NC>
+hx_status launch_prec(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s) {
+  if constexpr (MODE != MODE_MASS) {
+    if (op.kind == HX_HELMHOLTZ) return launch_prec_h<P, Q, MODE, NC, true>(op, prec, eout, a, s);
+  }
+  return launch_prec_h<P, Q, MODE, NC, false>(op, prec, eout, a, s);
 }
 
 template <int P, int Q, int MODE>

@@ -136,12 +136,14 @@ __device__ __forceinline__ void eo_apply_t(const T *__restrict__ C0, const T (&v
 }
 
 // ROWS: idx holds one base id per r1-row ([e][k][j], node (i, j, k) = base + i) instead of
-// one id per node.
-template <int P, int NC, typename T, typename TQ, bool EOUT, bool ROWS>
+// one id per node. HELM: the Helmholtz operator alpha A + beta B; qm [e][k][j][i] holds
+// beta * w * detJ at the nodes, where the collocated mass matrix is diagonal, so node (i, j, k)
+// adds qm * u to its sum (u read again at the end: the element's x values are still in the L2).
+template <int P, int NC, typename T, typename TQ, bool EOUT, bool ROWS, bool HELM = false>
 __global__ void __launch_bounds__(CollocCfg<P>::THREADS)
     k_colloc(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
              const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ order,
-             int64_t e_begin, int64_t e_end, const T *__restrict__ zero) {
+             int64_t e_begin, int64_t e_end, const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   using CF = CollocCfg<P>;
   constexpr int P2 = CF::P2, P3 = P2 * P, EPB = CF::EPB, LS = CF::LS, PL = CF::PL;
   __shared__ T s0[EPB][CF::BUF];
@@ -236,9 +238,22 @@ __global__ void __launch_bounds__(CollocCfg<P>::THREADS)
     T old[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) old[k] = *((EOUT || (ob & (1u << k))) ? zero : y + (int64_t)nid[k] * NC + c);
+    T hm[HELM ? P : 1], xm[HELM ? P : 1];
+    if constexpr (HELM) {
+      const TQ *const qme = qm + ee * P3 + b * P + a;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        hm[k] = ld_q<NC, TQ, T>(qme + k * P2);
+        xm[k] = x[(int64_t)nid[k] * NC + c];
+      }
+    }
     // transposed r3 derivative in registers: yt[m] = sum_k D[k][m] vt[k]
     T yt[P];
     eo_apply_t<P, T>(C, vt, yt);
+    if constexpr (HELM) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) yt[k] += hm[k] * xm[k];
+    }
     __syncthreads();
     // ---- transposed r1 derivative on S0 (thread (j=a, k=b)), r2 on S1 (thread (i=a, k=b)), in place
 #pragma unroll

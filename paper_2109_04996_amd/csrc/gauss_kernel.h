@@ -139,12 +139,15 @@ __device__ __forceinline__ void elem_sync() {
 // the wavefront, more a workgroup barrier).
 // ONEBUF (mass only): S1 is S0, one LDS buffer per element; the two passes that read one layout and
 // write another wait for every read before writing
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false>
+// HELM (diffusion only): the Helmholtz operator alpha A + beta B; qm [e][qc][qb][qa] = beta * w * detJ, and
+// the mass term qm * u joins the r3 line's sum before the transposed interpolations.
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false, bool HELM = false>
 __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool lane_live,
                                               int64_t e, int c, const TQ *__restrict__ qd, const T *__restrict__ tab,
                                               const T *__restrict__ x, const int32_t (&nid)[P], uint32_t ob,
                                               const T *__restrict__ zero, const T *__restrict__ y, T (&old)[P],
-                                              T (&z)[P]) {
+                                              T (&z)[P], const TQ *__restrict__ qm = nullptr) {
+  static_assert(!HELM || MODE == MODE_DIFF, "the Helmholtz mass term rides on the diffusion pipeline");
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
   constexpr int LS = Q + 1, PL = Q * LS;
 #define AT(i, j, k) ((k) * PL + (j) * LS + (i))
@@ -221,11 +224,16 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
       // r3 derivative on the r3 line of (qi = a, qj = b), kept in registers; r2 derivative on the
       // r2 line of (qi = a, qk = b), to S0 once every lane has read u
       T ut[Q];
+      T um[HELM ? Q : 1];  // u on the r3 line, kept for the Helmholtz mass term
       {
         T lk[Q];
 #pragma unroll
         for (int l = 0; l < Q; ++l) lk[l] = S0[AT(a, b, l)];
         deriv_fwd<Q, T>(tD, lk, ut);
+        if constexpr (HELM) {
+#pragma unroll
+          for (int l = 0; l < Q; ++l) um[l] = lk[l];
+        }
       }
       {
         T lj[Q], us[Q];
@@ -264,6 +272,11 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
         __builtin_amdgcn_sched_barrier(0);
       }
       deriv_bwd<Q, T>(tD, vt, w);  // r3 part, on the r3 line of (a, b)
+      if constexpr (HELM) {
+        const TQ *const qme = qm + e * Q3 + b * Q + a;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) w[k] += ld_q<NC, TQ, T>(qme + k * Q2) * um[k];
+      }
       elem_sync<NT>();
       // transposed r1 (thread (qj = a, qk = b), from S1) and r2 (thread (qi = a, qk = b), from S0)
       {
@@ -342,11 +355,11 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 
 // One element per workgroup. tab: interp [Q][P], D [Q][Q], then the even-odd coefficients of the
 // interpolation (EOInterp) and of D (EOLayout).
-template <int P, int Q, int MODE, int NC, typename T, typename TQ>
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool HELM = false>
 __global__ void __launch_bounds__(GaussCfg<Q>::NT)
     k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
-            const T *__restrict__ zero) {
+            const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
   static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
   constexpr int NT = GaussCfg<Q>::NT;
@@ -374,7 +387,8 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
 
   T old[P], z[P];
-  gauss_element<P, Q, MODE, NC, T, TQ, NT>(S0, S1, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y, old, z);
+  gauss_element<P, Q, MODE, NC, T, TQ, NT, false, HELM>(S0, S1, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y,
+                                                       old, z, qm);
   if (node_lane) {
 #pragma unroll
     for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
@@ -389,12 +403,13 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
 // IDX: node ids as in k_colloc_strip (0 per node, 1 per r1-row, 2 affine per element).
 // Mass keeps one LDS buffer per element (ONEBUF), and at q = 9 at most 64 registers: two 16-wavefront
 // workgroups then fit on a CU, against one with two buffers.
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX>
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
     __attribute__((amdgpu_waves_per_eu((MODE == MODE_MASS && Q == 9) ? 8 : 1)))
     k_gauss_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                   const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
-                  const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
+                  const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero,
+                  const TQ *__restrict__ qm = nullptr) {
   static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
   constexpr int NTE = GaussCfg<Q>::NT;  // threads per element
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
@@ -442,8 +457,8 @@ __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
   T *S1;
   if constexpr (ONEBUF) S1 = s0[w];
   else S1 = s1[w];
-  gauss_element<P, Q, MODE, NC, T, TQ, NTE, ONEBUF>(s0[w], S1, a, b, lane_live, ee, c, qd, tab, x, nid, ob, zero, y,
-                                                    old, z);
+  gauss_element<P, Q, MODE, NC, T, TQ, NTE, ONEBUF, HELM>(s0[w], S1, a, b, lane_live, ee, c, qd, tab, x, nid, ob, zero,
+                                                          y, old, z, qm);
   T out[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) out[k] = old[k] + z[k];

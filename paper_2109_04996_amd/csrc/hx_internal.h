@@ -115,6 +115,9 @@ struct hx_mesh_s {
   std::vector<int64_t> strip_color_start;  // nstrip_colors + 1, in strips
   hx::DevBuf<int32_t> strip_elems;         // [nstrips][kStrip], -1 past the strip's end
   hx::DevBuf<uint16_t> strip_own;          // [E_internal][P^2] bit k: first write of node (i,j,k) in strip order
+  // transpose of the element restriction (made on first use): the E-vector slots e*P^3 + l (caller
+  // element e, local node l) of each node, ascending; gather_ptr has nnodes + 1 entries
+  hx::DevBuf<int32_t> gather_ptr, gather_slot;
 };
 
 struct hx_op_s {
@@ -132,6 +135,10 @@ struct hx_op_s {
   int ncq = 1;          // stored values per quadrature point
   hx::DevBuf<double> qdata;    // [E_internal][ncq][Q^3]
   hx::DevBuf<float> qdata32;   // FP32 copy, made on demand
+  // HX_HELMHOLTZ: qdata holds alpha times the diffusion factors; qmass [E_internal][Q^3] beta w detJ
+  double alpha = 1.0, beta = 0.0;
+  hx::DevBuf<double> qmass;
+  hx::DevBuf<float> qmass32;   // FP32 copy, made with qdata32
   hx::DevBuf<double> tab;      // device 1D tables: interp [Q][P], grad [Q][P], colloc [Q][Q]
   hx::DevBuf<float> tab32;
   // solver workspace (allocated on first solve)
@@ -139,6 +146,7 @@ struct hx_op_s {
   hx::DevBuf<float> work32;
   hx::DevBuf<double> red;      // reduction partials and device scalars
   hx::DevBuf<double> diag;     // assembled diagonal (cached)
+  hx::DevBuf<double> evec;     // E-vector of the node-gather apply inside solves (made on first use)
   bool diag_valid = false;
   // coefficient parameters (kept for the element features of the learned preconditioner)
   int kappa_M = 0;
@@ -209,7 +217,11 @@ enum class Prec { F64, F32_Q64, F32_Q32 };
 hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyArgs &a, hipStream_t s);
 hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s, int *bad_det);
 hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
+hx_status launch_diagonal_tables(const hx_op_s &op, const double *interp, const double *grad, double *diag,
+                                 hipStream_t s);
 hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s);
+// the mesh's transpose restriction (gather_ptr, gather_slot), built on first call
+hx_status mesh_gather_csr(hx_mesh_s &m);
 // p-multigrid transfer between level l (fine) and l+1 on FP64 or FP32 vectors; fm: free mask applied to the
 // output, or null
 template <typename T>

@@ -7,7 +7,9 @@
 // and stored (partial assembly):
 //   mass       w detJ
 //   diffusion  w kappa detJ J^-1 J^-T = w kappa adj(J) adj(J)^T / detJ
-// stored as 6 symmetric entries per point, layout [e][qc][m][qb][qa] (plane by plane).
+// stored as 6 symmetric entries per point, layout [e][qc][m][qb][qa] (plane by plane);
+// the Helmholtz operator alpha A + beta B stores alpha times the diffusion entries and,
+// separately, beta w detJ.
 // Miniapps section (Nekbone's diagonal preconditioner): the diagonal of the
 // assembled operator is sum_e G_e^T diag(B^T D B), computed here point by
 // point from the 1D tables without forming element matrices.
@@ -30,10 +32,12 @@ struct KappaDev {
 
 // One block per element: stage the element's node coordinates in LDS, then
 // one thread per quadrature point.
+// HX_HELMHOLTZ: qd gets alpha times the diffusion factors and qm [e][qc][qb][qa] beta * w * detJ.
 __global__ void __launch_bounds__(kSetupThreads)
     k_qdata(int P, int Q, int kind, const int32_t *__restrict__ idx, const double *__restrict__ xyz,
             const double *__restrict__ interp, const double *__restrict__ grad, const double *__restrict__ qw,
-            KappaDev kap, double *__restrict__ qd, int *__restrict__ bad) {
+            KappaDev kap, double *__restrict__ qd, int *__restrict__ bad, double alpha, double beta,
+            double *__restrict__ qm) {
   __shared__ double sx[3][kMaxP * kMaxP * kMaxP];
   __shared__ double sI[kMaxQ * kMaxP], sG[kMaxQ * kMaxP], sw[kMaxQ];
   const int64_t e = blockIdx.x;
@@ -93,6 +97,7 @@ __global__ void __launch_bounds__(kSetupThreads)
     if (kind == HX_MASS) {
       out[0] = w * det;
     } else {
+      if (kind == HX_HELMHOLTZ) qm[e * (int64_t)Q3 + pt] = beta * (w * det);
       double kappa = 1.0;
       if (kap.M > 0) {
         double g = 0.0;
@@ -102,7 +107,7 @@ __global__ void __launch_bounds__(kSetupThreads)
         g *= sqrt(2.0 / kap.M);
         kappa = exp(kap.scale * g + kap.shift);
       }
-      const double s = w * kappa / det;
+      const double s = (kind == HX_HELMHOLTZ ? alpha : 1.0) * (w * kappa / det);
       // J^-1 = adj / det, so w kappa det J^-1 J^-T = s * adj adj^T
       double G[3][3];
       for (int r = 0; r < 3; ++r)
@@ -123,7 +128,7 @@ __global__ void __launch_bounds__(kSetupThreads)
 __global__ void __launch_bounds__(kSetupThreads)
     k_diag(int P, int Q, int kind, int ncomp, const int32_t *__restrict__ idx, const uint16_t *__restrict__ own,
            const double *__restrict__ interp, const double *__restrict__ grad, const double *__restrict__ qd,
-           double *__restrict__ diag, int64_t e_begin) {
+           double *__restrict__ diag, int64_t e_begin, const double *__restrict__ qm) {
   __shared__ double sI[kMaxQ * kMaxP], sG[kMaxQ * kMaxP];
   const int64_t e = e_begin + blockIdx.x;
   const int P2 = P * P, P3 = P2 * P, Q3 = Q * Q * Q;
@@ -153,6 +158,10 @@ __global__ void __launch_bounds__(kSetupThreads)
             const double d0 = Gi * Ij * Ik, d1 = Ii * Gj * Ik, d2 = Ii * Ij * Gk;
             s += g[0] * d0 * d0 + g[3 * Q2] * d1 * d1 + g[5 * Q2] * d2 * d2 +
                  2.0 * (g[Q2] * d0 * d1 + g[2 * Q2] * d0 * d2 + g[4 * Q2] * d1 * d2);
+            if (kind == HX_HELMHOLTZ) {
+              const double v = Ii * Ij * Ik;
+              s += qm[e * (int64_t)Q3 + (qc * Q + qb) * Q + qa] * v * v;
+            }
           }
         }
       }
@@ -192,26 +201,33 @@ hx_status launch_setup_qdata(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t
   HX_HIP(dBad.alloc(1));
   HX_HIP(hipMemsetAsync(dBad.ptr, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_qdata, dim3((unsigned)m.nelem), dim3(kSetupThreads), 0, s, op.P, op.Q, op.kind, m.idx.ptr,
-                     m.xyz.ptr, dI.ptr, dG.ptr, dW.ptr, kd, op.qdata.ptr, dBad.ptr);
+                     m.xyz.ptr, dI.ptr, dG.ptr, dW.ptr, kd, op.qdata.ptr, dBad.ptr, op.alpha, op.beta, op.qmass.ptr);
   HX_HIP(hipGetLastError());
   HX_HIP(hipMemcpyAsync(bad_det, dBad.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   HX_HIP(hipStreamSynchronize(s));
   return HX_OK;
 }
 
-hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s) {
+// the diagonal kernels on tables already in device memory (interp and grad, [Q][P] each); allocates nothing
+hx_status launch_diagonal_tables(const hx_op_s &op, const double *interp, const double *grad, double *diag,
+                                 hipStream_t s) {
   const hx_mesh_s &m = *op.mesh;
-  DevBuf<double> dI, dG;
-  HX_HIP(dI.upload(op.b.interp.data(), op.b.interp.size()));
-  HX_HIP(dG.upload(op.b.grad.data(), op.b.grad.size()));
   if (m.nuntouched > 0) HX_HIP(hipMemsetAsync(diag, 0, sizeof(double) * m.nnodes * op.ncomp, s));
   for (int c = 0; c < m.ncolors; ++c) {
     const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
     if (e1 <= e0) continue;
     hipLaunchKernelGGL(k_diag, dim3((unsigned)(e1 - e0)), dim3(kSetupThreads), 0, s, op.P, op.Q, op.kind, op.ncomp,
-                       m.idx.ptr, m.own.ptr, dI.ptr, dG.ptr, op.qdata.ptr, diag, e0);
+                       m.idx.ptr, m.own.ptr, interp, grad, op.qdata.ptr, diag, e0, op.qmass.ptr);
   }
   HX_HIP(hipGetLastError());
+  return HX_OK;
+}
+
+hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s) {
+  DevBuf<double> dI, dG;
+  HX_HIP(dI.upload(op.b.interp.data(), op.b.interp.size()));
+  HX_HIP(dG.upload(op.b.grad.data(), op.b.grad.size()));
+  if (hx_status st = launch_diagonal_tables(op, dI.ptr, dG.ptr, diag, s)) return st;
   // the temporary tables are freed when this returns: wait for the kernels that read them
   HX_HIP(hipStreamSynchronize(s));
   return HX_OK;
@@ -219,6 +235,10 @@ hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s) {
 
 hx_status make_qdata32(hx_op_s &op, hipStream_t s) {
   if (op.qdata32.ptr) return HX_OK;
+  if (op.qmass.count) {
+    HX_HIP(op.qmass32.alloc(op.qmass.count));
+    hipLaunchKernelGGL(k_d2f, dim3(1024), dim3(256), 0, s, (int64_t)op.qmass.count, op.qmass.ptr, op.qmass32.ptr);
+  }
   HX_HIP(op.qdata32.alloc(op.qdata.count));
   hipLaunchKernelGGL(k_d2f, dim3(1024), dim3(256), 0, s, (int64_t)op.qdata.count, op.qdata.ptr, op.qdata32.ptr);
   HX_HIP(hipGetLastError());

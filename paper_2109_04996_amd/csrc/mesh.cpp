@@ -495,6 +495,34 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
   return HX_OK;
 }
 
+namespace hx {
+
+// Transpose of the element restriction: for every node, the E-vector slots (caller element e, local node
+// l) -> e*P^3 + l that hold it, in ascending order (a counting sort over the caller elements), so a
+// gather sums a node's contributions in a fixed order.
+hx_status mesh_gather_csr(hx_mesh_s &m) {
+  if (m.gather_ptr.ptr) return HX_OK;
+  const int P3 = m.P * m.P * m.P;
+  const int64_t E = m.nelem, n = m.nnodes;
+  std::vector<int32_t> idx((size_t)E * P3);
+  HX_HIP(hipMemcpy(idx.data(), m.idx.ptr, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost));
+  std::vector<int32_t> pos_of(E);  // caller element -> internal position
+  for (int64_t t = 0; t < E; ++t) pos_of[m.order[t]] = (int32_t)t;
+  std::vector<int32_t> ptr(n + 1, 0), slot((size_t)E * P3);
+  for (const int32_t nd : idx) ++ptr[nd + 1];
+  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t ec = 0; ec < E; ++ec) {
+    const int32_t *row = idx.data() + (size_t)pos_of[ec] * P3;
+    for (int l = 0; l < P3; ++l) slot[fill[row[l]]++] = (int32_t)(ec * P3 + l);
+  }
+  HX_HIP(m.gather_ptr.upload(ptr.data(), ptr.size()));
+  HX_HIP(m.gather_slot.upload(slot.data(), slot.size()));
+  return HX_OK;
+}
+
+}  // namespace hx
+
 extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
   if (!m || !s) return hx::fail(HX_EINVAL, "null pointer");
   s->p = m->p;

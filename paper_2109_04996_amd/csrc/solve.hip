@@ -34,7 +34,7 @@ namespace {
 constexpr int kVecThreads = 256;
 constexpr int kVecBlocks = 1024;
 
-enum { S_RZ = 0, S_PAP, S_ALPHA, S_RZNEW, S_BETA, S_RR, S_FLAG, S_BB, S_TMP, S_NSCAL = 16 };
+enum { S_RZ = 0, S_PAP, S_ALPHA, S_RZNEW, S_BETA, S_RR, S_FLAG, S_BB, S_TMP, S_RZPREV, S_NSCAL = 16 };
 enum { FIN_SUM = 0, FIN_PAP, FIN_RZ_RR, FIN_RZ, FIN_FLEX };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -214,6 +214,112 @@ __global__ void __launch_bounds__(kVecThreads)
   }
 }
 
+// Sum of nb block partials in a fixed order, on every thread: the order of k_final, so every block of a
+// kernel that reduces the partials itself gets the bits k_final would have written.
+__device__ __forceinline__ double reduce_partials(const double *__restrict__ p, int nb) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) a += p[i];
+  return block_sum(a);
+}
+
+// The update of a PCG iteration with the step length reduced in place: every block sums the p'Ap
+// partials (part_pap, written by the dot kernel before it) itself, alpha = r'z / p'Ap, and block 0
+// keeps the scalars for the host's checks (p'Ap, alpha, and r'z of this step for the next kernel's beta).
+// Then as k_update: x += alpha p; r -= alpha m w; with JAC z = dinv r; partials r'z (JAC) and r'r;
+// rp (if given) = old r.
+template <typename T, int NC, bool JAC>
+__global__ void __launch_bounds__(kVecThreads)
+    k_update_red(int64_t n, double *__restrict__ S, const double *__restrict__ part_pap, int nb, T *__restrict__ x,
+                 const T *__restrict__ p, T *__restrict__ r, const T *__restrict__ w, const uint8_t *__restrict__ fm,
+                 const T *__restrict__ dinv, T *__restrict__ z, double *__restrict__ part_rz,
+                 double *__restrict__ part_rr, T *__restrict__ rp) {
+  const double pap = reduce_partials(part_pap, nb);
+  const bool ok = pap > 0.0 && isfinite(pap);
+  const double rz = S[S_RZ];
+  const double alpha_d = ok ? rz / pap : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S[S_PAP] = pap;
+    S[S_ALPHA] = alpha_d;
+    S[S_RZPREV] = rz;
+    if (!ok) S[S_FLAG] = 1.0;
+  }
+  const T alpha = (T)alpha_d;
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double srz = 0.0, srr = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    x[t] += alpha * p[t];
+    if (rp) rp[t] = r[t];
+    const T rv = is_free<NC>(fm, t) ? r[t] - alpha * w[t] : T(0);
+    r[t] = rv;
+    srr += (double)rv * (double)rv;
+    if constexpr (JAC) {
+      const T zv = dinv[t] * rv;
+      z[t] = zv;
+      srz += (double)rv * (double)zv;
+    }
+  }
+  srr = block_sum(srr);
+  if constexpr (JAC) srz = block_sum(srz);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = srr;
+    if constexpr (JAC) part_rz[blockIdx.x] = srz;
+  }
+}
+
+// p = z + beta p with beta reduced in place: every block sums the r'z partials (part_rz) and, for flexible
+// CG, the (r - r_prev)'z partials (part_flex); beta = r'z / r'z_prev (or (r - r_prev)'z / r'z_prev). Block 0
+// keeps r'z, r'r (part_rr) and beta for the host's checks and raises the breakdown flags as k_final does.
+template <typename T, bool FLEX>
+__global__ void __launch_bounds__(kVecThreads)
+    k_pupd_red(int64_t n, double *__restrict__ S, const double *__restrict__ part_rz,
+               const double *__restrict__ part_rr, const double *__restrict__ part_flex, int nb,
+               const T *__restrict__ z, T *__restrict__ p) {
+  const double rz = reduce_partials(part_rz, nb);
+  const double rr = reduce_partials(part_rr, nb);
+  const double num = FLEX ? reduce_partials(part_flex, nb) : rz;
+  const double rz_old = S[S_RZPREV];
+  const double beta_d = (rz_old != 0.0) ? num / rz_old : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S[S_RR] = rr;
+    S[S_RZNEW] = rz;
+    S[S_BETA] = beta_d;
+    S[S_RZ] = rz;
+    if (!(rz > 0.0) && rr > 0.0) S[S_FLAG] = 2.0;
+    if (FLEX ? (!isfinite(rz) || !isfinite(num)) : (!isfinite(rz) || !isfinite(rr))) S[S_FLAG] = 3.0;
+  }
+  const T beta = (T)beta_d;
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) p[t] = z[t] + beta * p[t];
+}
+
+// Node gather of an E-vector (the transpose of the element restriction): w[t] = sum of the node's slots in
+// ascending order (component c of slot e*P3 + l sits at (e*NC + c)*P3 + l), fused with the partial sums of
+// p'w over the same deterministic slices as k_dot.
+template <int NC>
+__global__ void __launch_bounds__(kVecThreads)
+    k_gather_dot(int64_t n, int P3, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gslot,
+                 const double *__restrict__ ye, const double *__restrict__ p, double *__restrict__ w,
+                 double *__restrict__ part) {
+  int64_t lo, hi;
+  slice(n, lo, hi);
+  double s = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const int64_t nd = NC == 1 ? t : t / NC;
+    const int c = NC == 1 ? 0 : (int)(t - nd * NC);
+    double v = 0.0;
+    for (int32_t k = gptr[nd]; k < gptr[nd + 1]; ++k) {
+      const int32_t sl = gslot[k];
+      v += NC == 1 ? ye[sl] : ye[((int64_t)(sl / P3) * NC + c) * P3 + sl % P3];
+    }
+    w[t] = v;
+    s += p[t] * v;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // p = z + beta p
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads) k_pupd(int64_t n, const double *__restrict__ S, const T *__restrict__ z,
@@ -359,7 +465,8 @@ struct Ctx {
   double *part0, *part1, *S, *part2;
   double *hS;  // pinned host copy of S
   int applies = 0;
-  bool graph = false;  // replay PCG iterations as a captured graph
+  bool graph = false;   // replay PCG iterations as a captured graph
+  bool gather = false;  // FP64 CG operator as an E-vector apply plus a node gather (HX_SCATTER_GATHER)
 };
 
 // Synchronises a stream when the scope ends (the solve is synchronous on every return path).
@@ -492,31 +599,58 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
   double rr = rr0;
   T *rp = flexible ? v.rp : nullptr;
   // one iteration: kernels only, every scalar device-resident (no host work between them)
+  // The scalars are reduced where they are used: the update kernel sums the p'Ap partials itself and
+  // the direction update the r'z (and r'r) partials, each block in the fixed order of k_final, so there
+  // is no single-block finishing kernel between them and the results are those of that sequence, bit
+  // for bit. Partials: p'Ap in part2; r'z in part0, r'r in part1, (r - r_prev)'z in part2 (flexible CG,
+  // after the update has read the p'Ap partials).
   auto iteration = [&]() -> hx_status {
-    if (hx_status st = apply_T(c, v.p, v.w, op_prec)) return st;
-    LAUNCH_V((k_dot<T>), c.n, v.p, v.w, c.part0);
-    FINAL(c.part0, (const double *)nullptr, FIN_PAP, 0);
+    bool dot_done = false;
+    if constexpr (std::is_same<T, double>::value) {
+      if (c.gather && op_prec == HX_FP64) {
+        // w = G^T (A_e p_e): one E-vector launch over all elements, then the node gather with p'w fused
+        ApplyArgs a{c.op.mesh->idx.ptr, c.op.mesh->own.ptr, nullptr, nullptr, nullptr, v.p, c.op.evec.ptr,
+                    c.op.mesh->order_d.ptr, 0, 0, c.op.mesh->nnodes};
+        ++c.applies;
+        if (hx_status st = launch_apply(c.op, Prec::F64, true, a, c.s)) return st;
+        const int P3 = c.op.P * c.op.P * c.op.P;
+        const int32_t *gp = c.op.mesh->gather_ptr.ptr, *gs = c.op.mesh->gather_slot.ptr;
+        if (c.nc == 1) LAUNCH_V((k_gather_dot<1>), c.n, P3, gp, gs, c.op.evec.ptr, v.p, v.w, c.part2);
+        else LAUNCH_V((k_gather_dot<3>), c.n, P3, gp, gs, c.op.evec.ptr, v.p, v.w, c.part2);
+        dot_done = true;
+      }
+    }
+    if (!dot_done) {
+      if (hx_status st = apply_T(c, v.p, v.w, op_prec)) return st;
+      LAUNCH_V((k_dot<T>), c.n, v.p, v.w, c.part2);
+    }
     const uint8_t *fm = c.op.mesh->freemask.ptr;
     if (!pc) {
-      if (c.nc == 1) LAUNCH_V((k_update<T, 1, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
-      else LAUNCH_V((k_update<T, 3, true>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
-      FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
+      if (c.nc == 1)
+        LAUNCH_V((k_update_red<T, 1, true>), c.n, c.S, c.part2, kVecBlocks, v.x, v.p, v.r, v.w, fm, v.dinv, v.z,
+                 c.part0, c.part1, rp);
+      else
+        LAUNCH_V((k_update_red<T, 3, true>), c.n, c.S, c.part2, kVecBlocks, v.x, v.p, v.r, v.w, fm, v.dinv, v.z,
+                 c.part0, c.part1, rp);
+      LAUNCH_V((k_pupd_red<T, false>), c.n, c.S, c.part0, c.part1, (const double *)nullptr, kVecBlocks, v.z, v.p);
     } else {
-      if (c.nc == 1) LAUNCH_V((k_update<T, 1, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
-      else LAUNCH_V((k_update<T, 3, false>), c.n, c.S, v.x, v.p, v.r, v.w, fm, v.dinv, v.z, c.part0, c.part1, rp);
+      if (c.nc == 1)
+        LAUNCH_V((k_update_red<T, 1, false>), c.n, c.S, c.part2, kVecBlocks, v.x, v.p, v.r, v.w, fm, v.dinv, v.z,
+                 c.part0, c.part1, rp);
+      else
+        LAUNCH_V((k_update_red<T, 3, false>), c.n, c.S, c.part2, kVecBlocks, v.x, v.p, v.r, v.w, fm, v.dinv, v.z,
+                 c.part0, c.part1, rp);
       if (hx_status st = (*pc)(v.r, v.z)) return st;
       if (flexible) {
         // Polak-Ribiere beta = (r - r_prev)'z / r_prev'z_prev keeps CG robust with a preconditioner
         // that is not exactly linear or symmetric (rounded operator)
-        FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_RR);
         LAUNCH_V((k_dot_flex<T>), c.n, v.r, v.rp, v.z, c.part0, c.part2);
-        FINAL(c.part0, c.part2, FIN_FLEX, 0);
+        LAUNCH_V((k_pupd_red<T, true>), c.n, c.S, c.part0, c.part1, c.part2, kVecBlocks, v.z, v.p);
       } else {
         LAUNCH_V((k_dot<T>), c.n, v.r, v.z, c.part0);
-        FINAL(c.part0, c.part1, FIN_RZ_RR, 0);
+        LAUNCH_V((k_pupd_red<T, false>), c.n, c.S, c.part0, c.part1, (const double *)nullptr, kVecBlocks, v.z, v.p);
       }
     }
-    LAUNCH_V((k_pupd<T>), c.n, c.S, v.z, v.p);
     HX_HIP(hipGetLastError());
     return HX_OK;
   };
@@ -834,6 +968,7 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->mlp_mode = 1;
   o->graph = 0;
   o->pmg = nullptr;
+  o->scatter = HX_SCATTER_COLORS;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
@@ -874,6 +1009,8 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     return fail(HX_EINVAL, "the IR inner solve runs in FP32: cheb_prec must be HX_FP32, HX_BF16 or HX_BF16_SPLIT");
   if (cheb && cheb_bf16 && (op->kind != HX_DIFFUSION || op->ncomp != 1))
     return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
+  if (o.scatter != HX_SCATTER_COLORS && o.scatter != HX_SCATTER_GATHER)
+    return fail(HX_EINVAL, "scatter must be HX_SCATTER_COLORS or HX_SCATTER_GATHER");
   *info = hx_solve_info{};
   hipStream_t s = static_cast<hipStream_t>(stream);
   // graph replay needs a stream that can be captured: the solve then runs on the operator's own
@@ -897,6 +1034,12 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   Ctx c{*op, s, n, NC, op->red.ptr, op->red.ptr + kVecBlocks, op->red.ptr + 3 * kVecBlocks,
         op->red.ptr + 2 * kVecBlocks, hs.p, 0};
   c.graph = use_graph;
+  if (o.scatter == HX_SCATTER_GATHER) {
+    const size_t ne = (size_t)op->mesh->nelem * NC * op->P * op->P * op->P;
+    if (op->evec.count < ne) HX_HIP(op->evec.alloc(ne));
+    if (hx_status st = mesh_gather_csr(*op->mesh)) return st;
+    c.gather = true;
+  }
 
   Vecs<double> v;
   if (hx_status st = carve(op->work, n, v)) return st;

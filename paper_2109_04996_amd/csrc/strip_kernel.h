@@ -52,11 +52,14 @@ struct StripCfg {
 // 1 one per r1-row (ROWS of k_colloc), 2 {base, s_j, s_k} per element, read with scalar loads
 // (node (i, j, k) = base + i + j s_j + k s_k), so the gather does not wait on a vector load.
 // sown: the strip-order ownership bits of each element.
-template <int P, int NC, typename T, typename TQ, int IDX>
+// HELM: the Helmholtz operator alpha A + beta B, with qm [e][k][j][i] = beta * w * detJ at the
+// nodes (the collocated mass matrix is diagonal), as in k_colloc.
+template <int P, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(StripCfg<P>::NW * 64)
     k_colloc_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                    const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y,
-                   const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero) {
+                   const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero,
+                   const TQ *__restrict__ qm = nullptr) {
   using SC = StripCfg<P>;
   constexpr int P2 = P * P, P3 = P2 * P, LS = P + 1, PL = P * LS, BUF = P * PL, SL = SC::SL, EPW = SC::EPW;
   __shared__ T s0[SL][BUF];
@@ -175,9 +178,22 @@ __global__ void __launch_bounds__(StripCfg<P>::NW * 64)
     T old[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
+    T hm[HELM ? P : 1], xm[HELM ? P : 1];
+    if constexpr (HELM) {
+      const TQ *const qme = qm + ee * P3 + b * P + a;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        hm[k] = ld_q<NC, TQ, T>(qme + k * P2);
+        xm[k] = x[(int64_t)nid[k] * NC + c];
+      }
+    }
     // transposed r3 derivative in registers: yt[m] = sum_k D[k][m] vt[k]
     T yt[P];
     eo_apply_t<P, T>(C, vt, yt);
+    if constexpr (HELM) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) yt[k] += hm[k] * xm[k];
+    }
     wave_sync();
     // ---- transposed r1 derivative on S0 (thread (j=a, k=b)), r2 on S1 (thread (i=a, k=b)), in place
 #pragma unroll

@@ -18,10 +18,11 @@ LIB_PATH = os.environ.get("HEXPA_LIB") or os.path.join(_PKG, "libhexpa.so")
 HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOWN, HX_EHIP, HX_ENOMEM = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 HX_GAUSS, HX_GLL = 0, 1
-HX_MASS, HX_DIFFUSION = 0, 1
+HX_MASS, HX_DIFFUSION, HX_HELMHOLTZ = 0, 1, 2
 HX_FP64, HX_FP32, HX_BF16, HX_BF16_SPLIT = 0, 1, 2, 3
 HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP, HX_PC_PMG = 0, 1, 2, 3, 4
 HX_SOLVE_FP64, HX_SOLVE_IR = 0, 1
+HX_SCATTER_COLORS, HX_SCATTER_GATHER = 0, 1
 
 STATUS_NAMES = {0: "HX_OK", -1: "HX_EINVAL", -2: "HX_ERANGE", -3: "HX_EUNSUPPORTED", -4: "HX_EGEOM",
                 -5: "HX_ENOCONV", -6: "HX_EBREAKDOWN", -7: "HX_EHIP", -8: "HX_ENOMEM"}
@@ -56,7 +57,8 @@ class hx_solve_opts(C.Structure):
                 ("cheb_ratio", C.c_double), ("cheb_prec", C.c_int), ("lanczos_steps", C.c_int),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
                 ("flexible", C.c_int), ("mlp", C.c_void_p), ("fallback", C.c_int), ("stall_window", C.c_int),
-                ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int), ("pmg", C.c_void_p)]
+                ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int), ("pmg", C.c_void_p),
+                ("scatter", C.c_int)]
 
 
 class hx_pmg_opts(C.Structure):
@@ -96,6 +98,8 @@ SIGNATURES = [
     ("hx_basis_get_tables", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("hx_basis_destroy", None, [_VP]),
     ("hx_op_create", C.c_int, [_VP, _VP, C.c_int, C.c_int, C.POINTER(hx_kappa_rff), _VP, C.POINTER(_VP)]),
+    ("hx_op_create_helmholtz", C.c_int, [_VP, _VP, C.c_int, C.c_double, C.c_double, C.POINTER(hx_kappa_rff), _VP,
+                                         C.POINTER(_VP)]),
     ("hx_op_apply", C.c_int, [_VP, _VP, _VP, _VP]),
     ("hx_op_apply_f32", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("hx_op_apply_bf16", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
@@ -240,18 +244,32 @@ def hx_basis_destroy(basis):
     load().hx_basis_destroy(basis)
 
 
+def _kappa_struct(kappa: dict | None):
+    """(hx_kappa_rff or None, arrays to keep alive during the call)."""
+    if kappa is None:
+        return None, None
+    om = np.ascontiguousarray(kappa["omega"], dtype=np.float64)
+    ph = np.ascontiguousarray(kappa["phase"], dtype=np.float64)
+    kp = hx_kappa_rff(om.shape[0], om.ctypes.data_as(C.POINTER(C.c_double)),
+                      ph.ctypes.data_as(C.POINTER(C.c_double)), float(kappa["scale"]), float(kappa["shift"]))
+    return kp, (om, ph)
+
+
 def hx_op_create(mesh, basis, kind, ncomp, kappa: dict | None = None, stream=None):
     h = C.c_void_p()
-    kp = None
-    keep = None
-    if kappa is not None:
-        om = np.ascontiguousarray(kappa["omega"], dtype=np.float64)
-        ph = np.ascontiguousarray(kappa["phase"], dtype=np.float64)
-        keep = (om, ph)
-        kp = hx_kappa_rff(om.shape[0], om.ctypes.data_as(C.POINTER(C.c_double)),
-                          ph.ctypes.data_as(C.POINTER(C.c_double)), float(kappa["scale"]), float(kappa["shift"]))
+    kp, keep = _kappa_struct(kappa)
     _check(load().hx_op_create(mesh, basis, kind, ncomp, C.byref(kp) if kp is not None else None, _stream(stream),
                                C.byref(h)), "hx_op_create")
+    del keep
+    return h
+
+
+def hx_op_create_helmholtz(mesh, basis, ncomp, alpha, beta, kappa: dict | None = None, stream=None):
+    h = C.c_void_p()
+    kp, keep = _kappa_struct(kappa)
+    _check(load().hx_op_create_helmholtz(mesh, basis, ncomp, float(alpha), float(beta),
+                                         C.byref(kp) if kp is not None else None, _stream(stream), C.byref(h)),
+           "hx_op_create_helmholtz")
     del keep
     return h
 

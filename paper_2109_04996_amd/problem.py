@@ -12,14 +12,16 @@ from . import hexpa as hx
 from . import inputs
 
 RULES = {"gauss": hx.HX_GAUSS, "gll": hx.HX_GLL}
-KINDS = {"mass": hx.HX_MASS, "diffusion": hx.HX_DIFFUSION}
+KINDS = {"mass": hx.HX_MASS, "diffusion": hx.HX_DIFFUSION, "helmholtz": hx.HX_HELMHOLTZ}
 
 
 class Problem:
-    """One operator on a lattice mesh: ``Problem(N, p, q, rule, kind, ncomp, warp, shuffle_seed, kappa)``."""
+    """One operator on a lattice mesh: ``Problem(N, p, q, rule, kind, ncomp, warp, shuffle_seed, kappa)``;
+    kind ``"helmholtz"`` is ``alpha A + beta B`` (``helmholtz=(alpha, beta)``)."""
 
     def __init__(self, N: int, p: int, q: int, rule: str, kind: str, ncomp: int = 1, warp="A",
-                 shuffle_seed=0, kappa: dict | None = None, dirichlet: bool = True, mesh: dict | None = None):
+                 shuffle_seed=0, kappa: dict | None = None, dirichlet: bool = True, mesh: dict | None = None,
+                 helmholtz=(1.0, 1.0)):
         import torch
         self.torch = torch
         self.N, self.p, self.q, self.rule, self.kind, self.ncomp = N, p, q, rule, kind, ncomp
@@ -28,7 +30,10 @@ class Problem:
         self.xyz = hx.hx_mesh_nodes_trilinear(p, m["elem_verts"], m["verts"], m["elem_nodes"], m["nnodes"])
         self.h_mesh = hx.hx_mesh_create(p, m["elem_nodes"], self.xyz, m["boundary"] if dirichlet else None)
         self.h_basis = hx.hx_basis_create(p, q, RULES[rule])
-        self.h_op = hx.hx_op_create(self.h_mesh, self.h_basis, KINDS[kind], ncomp, kappa)
+        if kind == "helmholtz":
+            self.h_op = hx.hx_op_create_helmholtz(self.h_mesh, self.h_basis, ncomp, helmholtz[0], helmholtz[1], kappa)
+        else:
+            self.h_op = hx.hx_op_create(self.h_mesh, self.h_basis, KINDS[kind], ncomp, kappa)
         self.n = m["nnodes"] * ncomp
         self.stats = hx.hx_mesh_get_stats(self.h_mesh)
 
@@ -100,19 +105,19 @@ class Problem:
 class Hierarchy:
     """p-multigrid over polynomial degrees on one lattice mesh.
 
-    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, ncomp, **pmg_opts)``:
+    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, ncomp, helmholtz, **pmg_opts)``:
     level l is a ``Problem`` of degree ``degrees[l]`` (strictly decreasing) with
     q = p + 1 GLL points or q = p + 2 Gauss points, on the same elements (same
     shuffle); ``meshes`` overrides the lattice meshes level by level.
     """
 
     def __init__(self, N: int, degrees, rule: str = "gll", kind: str = "diffusion", warp="A", shuffle_seed=0,
-                 kappa: dict | None = None, meshes=None, ncomp: int = 1, **pmg_opts):
+                 kappa: dict | None = None, meshes=None, ncomp: int = 1, helmholtz=(1.0, 1.0), **pmg_opts):
         self.levels = []
         for l, p in enumerate(degrees):
             q = p + 1 if rule == "gll" else p + 2
             self.levels.append(Problem(N, p, q, rule, kind, ncomp=ncomp, warp=warp, shuffle_seed=shuffle_seed,
-                                       kappa=kappa, mesh=None if meshes is None else meshes[l]))
+                                       kappa=kappa, mesh=None if meshes is None else meshes[l], helmholtz=helmholtz))
         self.h = hx.hx_pmg_create([pr.h_op for pr in self.levels], hx.hx_pmg_opts_default(**pmg_opts))
 
     @property

@@ -171,3 +171,25 @@ def test_chebyshev_action_matches_oracle(cheb_prec, tol):
         d = xv / np.linalg.norm(xv) - z / np.linalg.norm(z)
         assert np.linalg.norm(d) <= tol, np.linalg.norm(d)
         assert np.all(xv[~free] == 0)
+
+
+@pytest.mark.parametrize("N,p,q,rule,ncomp", [(4, 7, 8, "gll", 1), (4, 3, 5, "gauss", 1), (3, 5, 7, "gauss", 3),
+                                              (3, 6, 8, "gauss", 1)])
+def test_node_gather_cg_matches_colored(N, p, q, rule, ncomp):
+    # The CG operator as one E-vector launch plus a node gather with p'Ap fused (HX_SCATTER_GATHER):
+    # the same iteration as the colored scatter up to summation order -- iterations within 2, the same
+    # solution to the solve's own accuracy, deterministic bits, and the oracle's direct solution at 1e-12
+    mesh, pr, b, A, bo, free = _setup(N, p, q, rule, ncomp=ncomp, warp="B")
+    with pr:
+        x0, i0 = pr.solve(b, rtol=1e-10, check_every=1)
+        x1, i1 = pr.solve(b, rtol=1e-10, check_every=1, scatter=hx.HX_SCATTER_GATHER)
+        x2, i2 = pr.solve(b, rtol=1e-10, check_every=1, scatter=hx.HX_SCATTER_GATHER)
+        assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+        assert abs(i1["iterations"] - i0["iterations"]) <= 2, (i0, i1)
+        assert i1["true_rel_residual"] <= 1.05e-10
+        xd = solvers.direct_solve(A, bo, free)
+        x3, _ = pr.solve(b, rtol=1e-13, check_every=5, scatter=hx.HX_SCATTER_GATHER)
+        assert np.linalg.norm(x3.cpu().numpy() - xd) <= 1e-10 * np.linalg.norm(xd)
+        # graph replay of the gather iteration: bit for bit the eager one
+        x4, i4 = pr.solve(b, rtol=1e-10, check_every=1, scatter=hx.HX_SCATTER_GATHER, graph=1)
+        assert torch.equal(x1, x4) and i4["iterations"] == i1["iterations"]

@@ -276,3 +276,23 @@ def test_kappa_location_closed_form(N, p, q, tol):
     assert abs(y @ (A @ y) / I0 - 1.0) <= tol
     assert abs(x2 @ (A @ x2) / (4.0 * I2) - 1.0) <= tol
     assert abs(y2 @ (A @ y2) / (4.0 / 3.0 * I0) - 1.0) <= tol
+
+
+@pytest.mark.parametrize("rule,p,q", [("gauss", 3, 5), ("gll", 3, 4), ("gauss", 2, 3)])
+def test_helmholtz_forms(rule, p, q):
+    # alpha A + beta B: with u = x (the coordinate function, in V_h on any trilinear mesh)
+    # u^T (alpha A + beta B) u = alpha int |grad x|^2 + beta int x^2 = alpha + beta / 3 (exact for these rules);
+    # beta = 0 annihilates constants, alpha = 0 integrates 1 to beta times the volume; symmetric; positive
+    # definite for beta > 0 even without boundary conditions
+    mesh = lattice_mesh(3, p, warp="B", shuffle_seed=1)
+    X = fem.node_coordinates(mesh, p)
+    a, b = 0.7, 2.5
+    H = fem.assemble_helmholtz(mesh, p, q, rule, a, b)
+    x = X[:, 0]
+    assert abs(x @ (H @ x) - (a + b / 3.0)) <= 1e-12
+    one = np.ones(mesh["nnodes"])
+    assert np.abs(fem.assemble_helmholtz(mesh, p, q, rule, a, 0.0) @ one).max() <= 1e-12
+    assert abs(one @ (fem.assemble_helmholtz(mesh, p, q, rule, 0.0, b) @ one) - b) <= 1e-12
+    assert abs(H - H.T).max() <= 1e-14 * abs(H).max()
+    if mesh["nnodes"] <= 400:
+        assert np.linalg.eigvalsh(H.toarray())[0] > 0.0

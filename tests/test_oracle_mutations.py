@@ -30,6 +30,7 @@ MUTANTS = {
     "kappa_axes_swapped": ("fem.py", "wd = er.w3 * det * kappa_eval(kappa, x)",
                            "wd = er.w3 * det * kappa_eval(kappa, x[:, ::-1])"),
     "lambda_max_unscaled": ("solvers.py", "S = sp.diags(s) @ Aii @ sp.diags(s)", "S = Aii"),
+    "helmholtz_mass_scale": ("fem.py", "return (alpha * A + beta * B).tocsr()", "return (alpha * A + alpha * B).tocsr()"),
     "gll_weight_formula": ("quadrature.py", "w = 2.0 / (p * (p + 1) * Pp * Pp)", "w = 2.0 / (p * (p + 1) * Pp)"),
     "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * res)",
                               "d = rho_new * d + (2.0 * rho_new / delta) * (dinv * res)"),
@@ -42,7 +43,7 @@ MUTANTS = {
 PINS = {
     "fem.py": ("test_oracle_fem", ["test_mass_integrates_volume", "test_coordinate_function_forms",
                                    "test_diffusion_invariants", "test_collocated_diagonal_closed_form",
-                                   "test_kappa_location_closed_form"]),
+                                   "test_kappa_location_closed_form", "test_helmholtz_forms"]),
     "quadrature.py": ("test_oracle_quadrature", ["test_closed_forms", "test_exactness_degrees"]),
     "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial",
                                            "test_lambda_max_lanczos_branch"]),
