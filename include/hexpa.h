@@ -353,6 +353,31 @@ void hx_solve_opts_default(hx_solve_opts *opts);
 hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
                        hx_solve_info *info, hx_stream s);
 
+/* Largest nnodes*ncomp that hx_pcg_solve_noalloc accepts. */
+#define HX_NOALLOC_MAX_DOFS 1048576
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the FP64 Jacobi-preconditioned (or
+ * unpreconditioned) solve of hx_pcg_solve with every work vector, reduction
+ * partial and device scalar in one array of about 56 MiB that the library
+ * holds in static device memory, one copy per device, until the process ends.
+ * No hipMalloc, hipFree, pinned-host allocation or allocating library call is
+ * made; the caller passes b and x as for hx_pcg_solve, and the result is the
+ * same, bit for bit, as hx_pcg_solve's with the same opts.
+ *   opts: mode HX_SOLVE_FP64, precond HX_PC_NONE or HX_PC_JACOBI, scatter
+ *         HX_SCATTER_COLORS, graph 0 (other values: HX_EUNSUPPORTED).
+ *   op:   nnodes*ncomp <= HX_NOALLOC_MAX_DOFS (else HX_EINVAL, with the sizes
+ *         in hx_last_error()); its device must be the current one.
+ * The diagonal is the one an earlier hx_pcg_solve cached in op, else it is
+ * computed into the array on every call. Every call on one device shares that
+ * device's array and starts by clearing what it reads before writing: two
+ * calls that overlap on one device (two host threads, or two streams) race and
+ * give wrong results; serialise them. Synchronous, like hx_pcg_solve.
+ * Errors: HX_EINVAL, HX_EUNSUPPORTED, HX_ENOCONV (info filled), HX_EBREAKDOWN,
+ * HX_EHIP. */
+hx_status hx_pcg_solve_noalloc(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
+                               hx_solve_info *info, hx_stream s);
+
 /* ------------------------------------------------------------------------ */
 /* Two-layer network (learned element preconditioner; not in the paper)      */
 /* ------------------------------------------------------------------------ */

@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <random>
 #include <type_traits>
 
@@ -583,7 +584,8 @@ template <typename T>
 hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, double rr0, double stop2, int maxit,
                    int check_every, bool flexible, int *iters, double *rr_out, int stall_window = 0,
                    double stall_factor = 0.0) {
-  std::vector<std::pair<int, double>> hist{{0, rr0}};  // (iteration, r'r) at the host checks
+  std::vector<std::pair<int, double>> hist;  // (iteration, r'r) at the host checks (stall check only)
+  if (stall_window > 0) hist.emplace_back(0, rr0);
   HX_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * c.n, c.s));
   HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, c.s));
   flexible = flexible && pc;  // Jacobi is linear and symmetric: plain CG
@@ -1228,5 +1230,150 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   info->true_rel_residual = std::sqrt(rr_true) / bn;
   if (result == HX_OK && o.mode == HX_SOLVE_FP64 && info->rel_residual > o.rtol)
     result = fail(HX_ENOCONV, "PCG reached maxit without meeting rtol");
+  return result;
+}
+
+// ---------------------------------------------------------------- the solve that allocates nothing
+
+namespace {
+
+// Layout of the no-allocation solve's device memory, in doubles: the two 1D tables of the diagonal
+// kernel (interpolation and gradient, [q][p+1] each), the reduction partials and device scalars, and
+// seven vectors of up to HX_NOALLOC_MAX_DOFS entries (r, z, p, A p, D^-1, the correction, the diagonal).
+constexpr size_t kNaTab = 2 * kMaxQ * kMaxP;
+constexpr size_t kNaRedOff = 256;
+constexpr size_t kNaVecOff = kNaRedOff + ((3 * kVecBlocks + S_NSCAL + 31) / 32) * 32;
+constexpr size_t kNaDoubles = kNaVecOff + 7 * (size_t)HX_NOALLOC_MAX_DOFS;
+static_assert(kNaTab <= kNaRedOff, "tables overlap the reduction buffers");
+
+}  // namespace
+
+// Each device holds its own copy from the time the library's code is loaded on it until the process ends
+// (about 56 MiB). Host code must not pass this name to a kernel or a copy: in host code it is a stand-in,
+// not a device address. Host code uses the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on device dev (the current device), looked up once per device
+hx_status scratch_address(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HX_EUNSUPPORTED, "device ordinal beyond the supported range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HX_EHIP, "hipGetSymbolAddress returned a null address for the solver's scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return HX_OK;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_pcg_solve_noalloc(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
+                                          hx_solve_info *info, hx_stream stream) {
+  if (!op || !b || !x || !opts || !info) return fail(HX_EINVAL, "null argument");
+  const hx_solve_opts &o = *opts;
+  if (o.mode != HX_SOLVE_FP64) return fail(HX_EUNSUPPORTED, "the no-allocation solve runs in HX_SOLVE_FP64 mode");
+  if (o.precond != HX_PC_NONE && o.precond != HX_PC_JACOBI)
+    return fail(HX_EUNSUPPORTED, "the no-allocation solve supports HX_PC_NONE and HX_PC_JACOBI");
+  if (o.scatter != HX_SCATTER_COLORS) return fail(HX_EUNSUPPORTED, "the no-allocation solve needs HX_SCATTER_COLORS");
+  if (o.graph != 0) return fail(HX_EUNSUPPORTED, "the no-allocation solve does not replay graphs");
+  if (!(o.rtol > 0) || o.maxit < 1 || o.check_every < 1) return fail(HX_EINVAL, "need rtol > 0, maxit >= 1, check_every >= 1");
+  const int64_t n = op->mesh->nnodes * op->ncomp;
+  if (n > (int64_t)HX_NOALLOC_MAX_DOFS)
+    return fail(HX_EINVAL, "nnodes*ncomp = " + std::to_string(n) + " exceeds HX_NOALLOC_MAX_DOFS = " +
+                               std::to_string((long long)HX_NOALLOC_MAX_DOFS));
+  if (op->b.interp.size() + op->b.grad.size() > kNaTab) return fail(HX_EUNSUPPORTED, "1D tables exceed the scratch slot");
+  int dev = -1;
+  HX_HIP(hipGetDevice(&dev));
+  if (dev != op->mesh->device) return fail(HX_EINVAL, "current device differs from the operator's device");
+  double *sc = nullptr;
+  if (hx_status st = scratch_address(dev, &sc)) return st;
+
+  *info = hx_solve_info{};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  StreamSync solve_done;
+  solve_done.s = s;  // synchronous on every return path, like hx_pcg_solve
+  const int NC = op->ncomp;
+  const auto t_setup0 = std::chrono::steady_clock::now();
+  double hS[S_NSCAL] = {};  // host copy of the device scalars (pageable: nothing is allocated)
+  double *red = sc + kNaRedOff;
+  Ctx c{*op, s, n, NC, red, red + kVecBlocks, red + 3 * kVecBlocks, red + 2 * kVecBlocks, hS, 0};
+  double *vb = sc + kNaVecOff;
+  // r, z, p, w, dinv, (cd, ct unused), x, (rp, m unused): Jacobi PCG reads none of the unused ones
+  Vecs<double> v{vb, vb + n, vb + 2 * n, vb + 3 * n, vb + 4 * n, nullptr, nullptr, vb + 5 * n, nullptr, nullptr};
+  const double *dg = nullptr;
+  if (o.precond == HX_PC_JACOBI) {
+    if (op->diag_valid) {
+      dg = op->diag.ptr;  // the diagonal an earlier solve cached: already in memory the operator owns
+    } else {
+      // the diagonal into the seventh vector, its kernel reading the 1D tables staged in the scratch array
+      double *d = vb + 6 * n, *ti = sc, *tg = sc + op->b.interp.size();
+      HX_HIP(hipMemcpyAsync(ti, op->b.interp.data(), sizeof(double) * op->b.interp.size(), hipMemcpyHostToDevice, s));
+      HX_HIP(hipMemcpyAsync(tg, op->b.grad.data(), sizeof(double) * op->b.grad.size(), hipMemcpyHostToDevice, s));
+      if (hx_status st = launch_diagonal_tables(*op, ti, tg, d, s)) return st;
+      dg = d;
+    }
+  }
+  if (NC == 1) LAUNCH_V((k_dinv<double, 1>), n, dg, op->mesh->freemask.ptr, v.dinv);
+  else LAUNCH_V((k_dinv<double, 3>), n, dg, op->mesh->freemask.ptr, v.dinv);
+  HX_HIP(hipGetLastError());
+  HX_HIP(hipStreamSynchronize(s));
+  const auto t0 = std::chrono::steady_clock::now();
+  info->setup_seconds = std::chrono::duration<double>(t0 - t_setup0).count();
+
+  // the device scalars start at zero: an earlier call on this device left its own there
+  HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, s));
+  if (o.use_x0) {
+    if (NC == 1) LAUNCH_V((k_maskset<1>), n, op->mesh->freemask.ptr, x);
+    else LAUNCH_V((k_maskset<3>), n, op->mesh->freemask.ptr, x);
+  } else {
+    HX_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  }
+  if (NC == 1) LAUNCH_V((k_resid<double, double, 1>), n, 1.0, b, (const double *)nullptr, op->mesh->freemask.ptr, v.r, c.part1);
+  else LAUNCH_V((k_resid<double, double, 3>), n, 1.0, b, (const double *)nullptr, op->mesh->freemask.ptr, v.r, c.part1);
+  FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_BB);
+  if (hx_status st = read_scalars(c)) return st;
+  const double bb = c.hS[S_BB];
+  if (!std::isfinite(bb)) return fail(HX_EBREAKDOWN, "right-hand side is not finite");
+  if (bb == 0.0) {
+    HX_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    return HX_OK;
+  }
+  const double bn = std::sqrt(bb);
+  // v.r = m (b - A x); r'r
+  auto residual = [&](double *rr_out) -> hx_status {
+    if (hx_status st = apply_T(c, x, v.w, HX_FP64)) return st;
+    if (NC == 1) LAUNCH_V((k_resid<double, double, 1>), n, 1.0, b, v.w, op->mesh->freemask.ptr, v.r, c.part1);
+    else LAUNCH_V((k_resid<double, double, 3>), n, 1.0, b, v.w, op->mesh->freemask.ptr, v.r, c.part1);
+    HX_HIP(hipMemsetAsync(c.S, 0, sizeof(double) * S_NSCAL, s));
+    FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_RR);
+    if (hx_status st = read_scalars(c)) return st;
+    *rr_out = c.hS[S_RR];
+    return HX_OK;
+  };
+  double rr = 0.0;
+  if (hx_status st = residual(&rr)) return st;
+  int it = 0;
+  double rre = 0.0;
+  hx_status result = pcg_core<double>(c, v, nullptr, HX_FP64, rr, o.rtol * o.rtol * bb, o.maxit, o.check_every,
+                                      false, &it, &rre);
+  LAUNCH_V((k_axpy<double>), n, 1.0, v.x, x);
+  HX_HIP(hipGetLastError());
+  info->iterations = it;
+  info->rel_residual = std::sqrt(rre) / bn;
+  HX_HIP(hipStreamSynchronize(s));
+  info->solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  info->operator_applies = c.applies;
+  double rr_true = 0.0;
+  if (hx_status st = residual(&rr_true)) return st;
+  info->true_rel_residual = std::sqrt(rr_true) / bn;
+  if (result == HX_OK && info->rel_residual > o.rtol) result = fail(HX_ENOCONV, "PCG reached maxit without meeting rtol");
   return result;
 }

@@ -123,6 +123,7 @@ SIGNATURES = [
     ("hx_op_mlp_targets", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hx_op_mlp_precond", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("hx_pcg_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(hx_solve_opts), C.POINTER(hx_solve_info), _VP]),
+    ("hx_pcg_solve_noalloc", C.c_int, [_VP, _VP, _VP, C.POINTER(hx_solve_opts), C.POINTER(hx_solve_info), _VP]),
     ("hx_pmg_opts_default", None, [C.POINTER(hx_pmg_opts)]),
     ("hx_pmg_create", C.c_int, [_VP, C.c_int, C.POINTER(hx_pmg_opts), _VP, C.POINTER(_VP)]),
     ("hx_pmg_levels", C.c_int, [_VP]),
@@ -314,14 +315,25 @@ def hx_solve_opts_default(**overrides) -> hx_solve_opts:
     return o
 
 
-def hx_pcg_solve(op, b, x, opts: hx_solve_opts, stream=None, raise_on_error=True):
+def _solve(name, op, b, x, opts: hx_solve_opts, stream, raise_on_error):
     info = hx_solve_info()
-    code = load().hx_pcg_solve(op, _ptr(b), _ptr(x), C.byref(opts), C.byref(info), _stream(stream))
+    code = getattr(load(), name)(op, _ptr(b), _ptr(x), C.byref(opts), C.byref(info), _stream(stream))
     d = {k: getattr(info, k) for k, _ in info._fields_}
     d["status"] = STATUS_NAMES.get(code, code)
     if raise_on_error and code != HX_OK:
-        raise HexpaError(code, "hx_pcg_solve", hx_last_error())
+        raise HexpaError(code, name, hx_last_error())
     return d
+
+
+def hx_pcg_solve(op, b, x, opts: hx_solve_opts, stream=None, raise_on_error=True):
+    return _solve("hx_pcg_solve", op, b, x, opts, stream, raise_on_error)
+
+
+HX_NOALLOC_MAX_DOFS = 1048576
+
+
+def hx_pcg_solve_noalloc(op, b, x, opts: hx_solve_opts, stream=None, raise_on_error=True):
+    return _solve("hx_pcg_solve_noalloc", op, b, x, opts, stream, raise_on_error)
 
 
 # ---------------------------------------------------------------------------- p-multigrid
