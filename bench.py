@@ -91,6 +91,48 @@ def copy_probe(nbytes=4 << 30):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def read_heavy_probe(nbytes=4 << 30, parts=8):
+    """Device bandwidth of a read-dominated stream: y = sum of ``parts`` slices of one buffer (``parts``
+    reads per write, 8 of 9 bytes read for parts = 8, the mix of the diffusion apply)."""
+    import torch
+    m = nbytes // 8 // parts
+    a = torch.empty(parts, m, dtype=torch.float64, device="cuda").uniform_()
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        torch.sum(a, dim=0, out=y)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    ev0.record()
+    for _ in range(reps):
+        torch.sum(a, dim=0, out=y)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, y
+    torch.cuda.empty_cache()
+    return (parts + 1) * m * 8 / (ms * 1e-3) / 1e9
+
+
+def apply_line(pr, ab, dofs, steps=50, warmup=5, x=None):
+    """Time ``steps`` applies of an operator (HIP events on the launch stream) and express the rate
+    against the algorithmic bytes ``ab`` (bytes per apply)."""
+    import torch
+
+    from paper_2109_04996_amd.inputs import uniform_vector
+    x = pr.to_dev(uniform_vector(pr.mesh["nnodes"], 1, pr.ncomp)) if x is None else x
+    y = pr.zeros()
+    total_ms, _, per = time_applies(pr, x, y, steps, warmup)
+    ms = total_ms / steps
+    del x, y
+    return dict(ms_per_apply=round(ms, 4), median_ms=round(per[len(per) // 2], 4), gdofs=round(dofs / ms / 1e6, 3),
+                algorithmic_bytes_per_dof=round(ab / dofs, 2),
+                achieved_GBs=round(ab / (ms * 1e-3) / 1e9, 1), frac=round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                index_mode=pr.stats["index_mode"], strips=pr.stats["nstrips"],
+                strip_groups=pr.stats["nstrip_groups"],
+                launches_per_apply=pr.stats["nstrip_colors"] if pr.stats["nstrips"] > 0 else pr.stats["ncolors"])
+
+
 def pmg_degrees(p):
     """Halving degree schedule of the p-multigrid hierarchy: p, p // 2, ..., 1."""
     d = [p]
@@ -334,42 +376,55 @@ CG_SWEEP_N = (2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48)
 def cg_sweep(label="BP5", p=7, q=8, rule="gll", Ns=CG_SWEEP_N, short=20, long=60):
     """Throughput per CG iteration against problem size (the strong-scale limit on one GPU):
     FP64 Jacobi-PCG on BP5 (q = p+1 GLL) or BP3 (q = p+2 Gauss), mesh A, Dirichlet, b a seeded
-    random vector on the free nodes,
-    timed as the difference of a long and a short run, so the setup, the first residual and the
-    final checks cancel. One JSON line per size, then r_max, n_0.8 and t_0.8 (the largest
-    throughput, the smallest n reaching 80% of it, and its time per iteration)."""
+    random vector on the free nodes, with the CG operator in both forms: the colored scatter (one
+    launch per color) and the E-vector apply plus a node gather with p'Ap fused (two launches).
+    Each is timed as the difference of a long and a short run, so the setup, the first residual and
+    the final checks cancel. One JSON line per size, then r_max, n_0.8 and t_0.8 (the largest
+    throughput, the smallest n reaching 80% of it, and its time per iteration) for each form and for
+    the faster of the two at each size."""
     import numpy as np
     import torch
 
+    from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
     from paper_2109_04996_amd.problem import Problem
+    forms = {"colors": hx.HX_SCATTER_COLORS, "gather": hx.HX_SCATTER_GATHER}
     rows = []
     for N in Ns:
         mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
         with Problem(N, p, q, rule, "diffusion", mesh=mesh) as pr:
             free = pr.to_dev((mesh["boundary"] == 0).astype(np.float64))
             b = pr.to_dev(uniform_vector(mesh["nnodes"], 2)) * free
-            t = {}
-            for k in (short, long):
-                best = None
-                for _ in range(3):
-                    torch.cuda.synchronize()
-                    x, info = pr.solve(b, rtol=1e-30, maxit=k, check_every=k, raise_on_error=False)
-                    if info["iterations"] != k:
-                        raise RuntimeError(f"CG stopped after {info['iterations']} of {k} iterations at N={N}")
-                    best = info["solve_seconds"] if best is None else min(best, info["solve_seconds"])
-                t[k] = best
-            per_it = (t[long] - t[short]) / (long - short)
             n = mesh["nnodes"]
-            rec = dict(cg_sweep=label, p=p, q=q, N=N, dofs=n, dofs_paper=mesh["nelem"] * p ** 3,
-                       us_per_iteration=round(per_it * 1e6, 2), gdofs_per_iteration=round(n / per_it / 1e9, 3))
+            rec = dict(cg_sweep=label, p=p, q=q, N=N, dofs=n, dofs_paper=mesh["nelem"] * p ** 3)
+            for fname, sc in forms.items():
+                t = {}
+                for k in (short, long):
+                    best = None
+                    for _ in range(3):
+                        torch.cuda.synchronize()
+                        x, info = pr.solve(b, rtol=1e-30, maxit=k, check_every=k, raise_on_error=False, scatter=sc)
+                        if info["iterations"] != k:
+                            raise RuntimeError(f"CG stopped after {info['iterations']} of {k} iterations at N={N}")
+                        best = info["solve_seconds"] if best is None else min(best, info["solve_seconds"])
+                    t[k] = best
+                per_it = (t[long] - t[short]) / (long - short)
+                rec[f"us_per_iteration_{fname}"] = round(per_it * 1e6, 2)
+                rec[f"gdofs_per_iteration_{fname}"] = round(n / per_it / 1e9, 3)
+            best = min(forms, key=lambda f: rec[f"us_per_iteration_{f}"])
+            rec["us_per_iteration"] = rec[f"us_per_iteration_{best}"]
+            rec["gdofs_per_iteration"] = rec[f"gdofs_per_iteration_{best}"]
+            rec["faster"] = best
             rows.append(rec)
             print(json.dumps(rec), flush=True)
-    rmax = max(r["gdofs_per_iteration"] for r in rows)
-    n08 = min((r for r in rows if r["gdofs_per_iteration"] >= 0.8 * rmax), key=lambda r: r["dofs"])
-    print(json.dumps(dict(cg_sweep_summary=label, p=p, q=q, r_max_gdofs=rmax, n_0_8=n08["dofs"],
-                          t_0_8_us=n08["us_per_iteration"],
-                          min_us_per_iteration=min(r["us_per_iteration"] for r in rows))), flush=True)
+    summary = dict(cg_sweep_summary=label, p=p, q=q)
+    for suffix in ("_colors", "_gather", ""):
+        rmax = max(r["gdofs_per_iteration" + suffix] for r in rows)
+        n08 = min((r for r in rows if r["gdofs_per_iteration" + suffix] >= 0.8 * rmax), key=lambda r: r["dofs"])
+        summary.update({f"r_max_gdofs{suffix}": rmax, f"n_0_8{suffix}": n08["dofs"],
+                        f"t_0_8_us{suffix}": n08["us_per_iteration" + suffix],
+                        f"min_us_per_iteration{suffix}": min(r["us_per_iteration" + suffix] for r in rows)})
+    print(json.dumps(summary), flush=True)
 
 
 def sweep(steps=20, warmup=3):
@@ -418,29 +473,127 @@ def sweep(steps=20, warmup=3):
             torch.cuda.empty_cache()
 
 
-def cpu_baseline(p: int, budget_s: float = 20.0):
-    """The oracle (scipy CSR SpMV of the assembled matrix) on a bounded sample of the same workload."""
-    import numpy as np
+def _oracle_threads() -> int:
+    """Host threads the oracle's SpMV uses: the cores this process may run on, at most 16 (the host
+    share of one GPU on the measurement boxes)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
-    from oracle import fem
+
+def cpu_baseline(p: int, budget_s: float = 6.0):
+    """The oracle on bounded samples of the same workload, on the host cores: the assembled-matrix SpMV
+    (scipy CSR, one thread and all threads over row blocks), and the oracle's Jacobi-PCG to 1e-8 beside
+    the GPU's on the same small problems (the CPU-scale configuration, N=4 p=3 q=5 Gauss, and BP5 p=7 on
+    6^3 elements)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    from oracle import fem, solvers
     from paper_2109_04996_amd.inputs import lattice_mesh, uniform_vector
+    from paper_2109_04996_amd.problem import Problem
     N = 6
     t0 = time.perf_counter()
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
-    A = fem.assemble(mesh, p, p + 1, "gll", "diffusion")
+    A = fem.assemble(mesh, p, p + 1, "gll", "diffusion").tocsr()
     t_asm = time.perf_counter() - t0
-    x = uniform_vector(mesh["nnodes"], 1)
-    reps, t = 0, 0.0
-    while t < budget_s * 0.5 and reps < 200:
-        t1 = time.perf_counter()
-        A @ x
-        t += time.perf_counter() - t1
-        reps += 1
     n = mesh["nnodes"]
-    return dict(value=round(n * reps / t / 1e9, 5), unit="GDOF/s", cores=1, kind="oracle",
-                sample=f"oracle scipy CSR SpMV (single thread) of the assembled BP5 p={p} q={p + 1} GLL matrix, "
-                       f"mesh A {N}^3 elements, {n} DOFs, nnz {A.nnz}, {reps} applies in {t:.2f} s; "
-                       f"assembly {t_asm:.1f} s excluded")
+    x = uniform_vector(n, 1)
+
+    def rate(fn):
+        fn()
+        reps, t = 0, 0.0
+        while t < budget_s and reps < 400:
+            t1 = time.perf_counter()
+            fn()
+            t += time.perf_counter() - t1
+            reps += 1
+        return n * reps / t / 1e9, reps, t
+
+    r1, reps1, t1 = rate(lambda: A @ x)
+    nt = _oracle_threads()
+    cuts = np.linspace(0, n, nt + 1).astype(np.int64)
+    blocks = [A[cuts[i]:cuts[i + 1]] for i in range(nt)]
+    y = np.empty(n)
+
+    def part(i):
+        y[cuts[i]:cuts[i + 1]] = blocks[i] @ x
+
+    with ThreadPoolExecutor(nt) as ex:
+        rn, repsn, tn = rate(lambda: list(ex.map(part, range(nt))))
+    assert np.allclose(y, A @ x, rtol=1e-13, atol=1e-13 * np.abs(y).max())
+    out = dict(value=round(rn, 5), unit="GDOF/s", cores=nt, kind="oracle",
+               sample=f"oracle scipy CSR SpMV of the assembled BP5 p={p} q={p + 1} GLL matrix, mesh A {N}^3 "
+                      f"elements, {n} DOFs, nnz {A.nnz}: {nt} threads over row blocks, {repsn} applies in "
+                      f"{tn:.2f} s; assembly {t_asm:.1f} s excluded",
+               one_core_value=round(r1, 5), one_core_sample=f"the same SpMV on one thread, {reps1} applies in {t1:.2f} s")
+
+    # the oracle's Jacobi-PCG (one thread) and the GPU's on the same problems, b = B f^, rtol 1e-8
+    pcg = []
+    for (Np, pp, q, rule) in ((4, 3, 5, "gauss"), (N, p, p + 1, "gll")):
+        m = mesh if (Np, pp) == (N, p) else lattice_mesh(Np, pp, warp="A", shuffle_seed=0)
+        X = fem.node_coordinates(m, pp)
+        f = 3 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+        Ao = A if (Np, pp) == (N, p) else fem.assemble(m, pp, q, rule, "diffusion").tocsr()
+        bo = fem.assemble(m, pp, pp + 2, "gauss", "mass") @ f
+        free = solvers.free_mask(m["boundary"])
+        t2 = time.perf_counter()
+        xo, ito, reso = solvers.jacobi_pcg(Ao, bo, free, tol=1e-8)
+        t_or = time.perf_counter() - t2
+        with Problem(Np, pp, q, rule, "diffusion", mesh=m) as pr, \
+                Problem(Np, pp, pp + 2, "gauss", "mass", mesh=m) as pm:
+            Xg = pr.xyz
+            b = pm.apply(pr.to_dev(3 * np.pi ** 2 * np.sin(np.pi * Xg[:, 0]) * np.sin(np.pi * Xg[:, 1])
+                                   * np.sin(np.pi * Xg[:, 2])))
+            pr.solve(b, rtol=1e-8)  # warm-up (diagonal, buffers)
+            torch.cuda.synchronize()
+            xg, info = pr.solve(b, rtol=1e-8, check_every=10)
+            xg = xg.cpu().numpy()
+        pcg.append(dict(problem=f"diffusion p={pp} q={q} {rule}, mesh A {Np}^3, {m['nnodes']} DOFs, b = B f^, "
+                                f"rtol 1e-8", oracle_seconds=round(t_or, 4), oracle_iterations=int(ito),
+                        oracle_threads=1, gpu_seconds=round(info["solve_seconds"], 5),
+                        gpu_iterations=info["iterations"],
+                        gpu_vs_oracle_rel_diff=float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))))
+    out["pcg"] = pcg
+    return out
+
+
+def extra_lines(out, mesh, N, p, roof):
+    """Apply lines beside the headline on the same 48^3 lattice: the general index path (20% of the
+    elements rotated, so the kernels read the full element restriction), BP6 (3-component collocated
+    diffusion) and the fused Helmholtz operator alpha A + beta B (collocated mass as a diagonal term)."""
+    import torch
+
+    from paper_2109_04996_amd.inputs import rotate_elements
+    from paper_2109_04996_amd.problem import Problem
+    Q = p + 1
+    E, n = mesh["nelem"], mesh["nnodes"]
+    print("[bench] general index path (20% of elements rotated)", file=sys.stderr, flush=True)
+    rot = rotate_elements(mesh, p, 0.2, seed=5)
+    with Problem(N, p, Q, "gll", "diffusion", mesh=rot) as pg:
+        ab = algorithmic_bytes(n, E, p + 1, Q)
+        roof["general_path"] = dict(workload=f"BP5 p={p} N={N} with 20% of the elements rotated (seed 5): full "
+                                             "element restriction", **apply_line(pg, ab["total"], n))
+    del rot
+    torch.cuda.empty_cache()
+    print("[bench] BP6 vector apply", file=sys.stderr, flush=True)
+    with Problem(N, p, Q, "gll", "diffusion", ncomp=3, mesh=mesh) as p6:
+        ab = algorithmic_bytes(n, E, p + 1, Q, 6, 3)
+        out["bp6"] = dict(workload=f"BP6 3-component diffusion apply, p={p}, q={Q} GLL-collocated, FP64, mesh A "
+                                   f"{N}^3, {n} nodes x 3 interleaved", bound="hbm", peak=HBM_PEAK_GBS,
+                          **apply_line(p6, ab["total"], 3 * n))
+    torch.cuda.empty_cache()
+    print("[bench] Helmholtz apply", file=sys.stderr, flush=True)
+    with Problem(N, p, Q, "gll", "helmholtz", mesh=mesh, helmholtz=(1.0, 1.0)) as ph:
+        ab = algorithmic_bytes(n, E, p + 1, Q, 7, 1)
+        out["helmholtz"] = dict(workload=f"fused alpha A + beta B (alpha = beta = 1), p={p}, q={Q} GLL-collocated "
+                                         f"(mass diagonal), FP64, mesh A {N}^3, {n} DOFs", bound="hbm",
+                                peak=HBM_PEAK_GBS, **apply_line(ph, ab["total"], n))
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -452,6 +605,8 @@ def main():
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-lines", action="store_true",
+                    help="skip the general-index-path, BP6 vector and Helmholtz apply lines")
     ap.add_argument("--copy-probe", action="store_true", help="(the copy probe always runs; kept for old commands)")
     ap.add_argument("--all", action="store_true",
                     help="also run the vector-IR, variable-coefficient Chebyshev and learned-preconditioner suites")
@@ -605,10 +760,20 @@ def main():
                            strips=pr.stats["nstrips"], launches_per_apply=ncol),
                median_ms=round(per[len(per) // 2], 4), p10_ms=round(per[len(per) // 10], 4),
                p90_ms=round(per[(9 * len(per)) // 10], 4), roofline=roof)
-    # the same algorithmic rate against a measured device-to-device copy of 4 GiB (read + write)
+    # the same algorithmic rate against a measured device-to-device copy of 4 GiB (read + write), and
+    # against a read-heavy stream of 8 reads per write (the apply's mix: 89% of its bytes are reads)
     cp = copy_probe()
     roof["copy_probe_GBs"] = round(cp, 1)
     roof["frac_vs_copy"] = round(achieved / cp, 4)
+    rh = read_heavy_probe()
+    roof["read_heavy_probe_GBs"] = round(rh, 1)
+    roof["frac_vs_read_heavy_probe"] = round(achieved / rh, 4)
+    # the affine node numbering moves 16 bytes of index per element instead of 4 (p+1)^3
+    if pr.stats["index_mode"] == 2:
+        moved = ab["total"] - ab["index"] + 16 * E
+        roof["frac_bytes_moved"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        roof["bytes_moved_per_dof"] = round(moved / n, 2)
+    roof["target_frac"] = 0.60
     if not a.no_solves:
         mass_pr = Problem(N, p, p + 2, "gauss", "mass", mesh=mesh)
         out["solves"] = dict(workload=f"BP5 p={p} N={N} Dirichlet, b = B f^, f = 3 pi^2 sin sin sin, rtol 1e-8",
@@ -616,6 +781,8 @@ def main():
         mass_pr.close()
     pr.close()
     del x, y
+    if not a.no_extra_lines:
+        extra_lines(out, mesh, N, p, roof)
     if a.all:
         torch.cuda.empty_cache()
         out["vector_ir"] = suite_vector_ir()

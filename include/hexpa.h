@@ -128,6 +128,8 @@ typedef struct {
                            the degree-7 collocated apply scatters together (0: the
                            per-element scatter is used)                          */
   int64_t nstrip_colors; /* strip colors (launches per apply when nstrips > 0)   */
+  int64_t nstrip_groups; /* workgroups per apply of the strip kernels: whole strips
+                            of one color packed into groups of up to 8 elements  */
   int index_mode;       /* element restriction read by the fused kernels: 0 the full
                            index array; 1 one id per r1-row (every r1-row of every
                            element holds consecutive ids); 2 three numbers per

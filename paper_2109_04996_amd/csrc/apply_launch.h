@@ -16,12 +16,12 @@ namespace hx {
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT, bool HELM = false>
 hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const ApplyArgs &a, hipStream_t s,
                         const TQ *qm = nullptr) {
-  // strips (one workgroup per strip and component)
+  // strips (one workgroup per group of whole strips and component)
   if constexpr (MODE == MODE_COLLOC && colloc_strips(P) && !EOUT) {
     const hx_mesh_s &m = *op.mesh;
     // below degree 7 a strip workgroup has 1-4 wavefronts: a launch needs two strips per CU on
     // average to fill the chip, else the element kernel (more, smaller workgroups) is faster
-    if (m.nstrips > 0 && (P == kStripP || m.nstrips >= (int64_t)kMinStripsPerColor * m.nstrip_colors)) {
+    if (m.nstrips > 0 && (P == kStripP || m.nstrip_groups >= (int64_t)kMinStripsPerColor * m.nstrip_colors)) {
       // strip scatter: one launch per strip color
       const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
       for (int c = 0; c < m.nstrip_colors; ++c) {
@@ -30,15 +30,15 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
         const dim3 grid((unsigned)((s1 - s0) * NC)), block(StripCfg<P>::NW * 64);
         if (m.idx_affine.ptr)
           hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 2, HELM>), grid, block, 0, s, m.idx_affine.ptr, m.strip_own.ptr,
-                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, m.strip_link.ptr, s0, zero,
                              qm);
         else if (m.idx_rows.ptr)
           hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 1, HELM>), grid, block, 0, s, m.idx_rows.ptr, m.strip_own.ptr,
-                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, m.strip_link.ptr, s0, zero,
                              qm);
         else
           hipLaunchKernelGGL((k_colloc_strip<P, NC, T, TQ, 0, HELM>), grid, block, 0, s, a.idx, m.strip_own.ptr, qd, tab,
-                             static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0, zero, qm);
+                             static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, m.strip_link.ptr, s0, zero, qm);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "k_colloc_strip launch");
@@ -87,14 +87,14 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
         if (m.idx_affine.ptr)
           hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 2, HELM>), grid, block, 0, s, m.idx_affine.ptr,
                              m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                             m.strip_elems.ptr, s0, zero, qm);
+                             m.strip_elems.ptr, m.strip_link.ptr, s0, zero, qm);
         else if (m.idx_rows.ptr)
           hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 1, HELM>), grid, block, 0, s, m.idx_rows.ptr,
                              m.strip_own.ptr, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                             m.strip_elems.ptr, s0, zero, qm);
+                             m.strip_elems.ptr, m.strip_link.ptr, s0, zero, qm);
         else
           hipLaunchKernelGGL((k_gauss_strip<P, Q, MODE, NC, T, TQ, 0, HELM>), grid, block, 0, s, a.idx, m.strip_own.ptr,
-                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, s0,
+                             qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), m.strip_elems.ptr, m.strip_link.ptr, s0,
                              zero, qm);
       }
       hipError_t e = hipGetLastError();

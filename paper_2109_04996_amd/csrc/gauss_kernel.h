@@ -408,8 +408,8 @@ __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
     __attribute__((amdgpu_waves_per_eu((MODE == MODE_MASS && Q == 9) ? 8 : 1)))
     k_gauss_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                   const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
-                  const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero,
-                  const TQ *__restrict__ qm = nullptr) {
+                  const int32_t *__restrict__ selems, const uint8_t *__restrict__ slink, int64_t s_begin,
+                  const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
   constexpr int NTE = GaussCfg<Q>::NT;  // threads per element
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
@@ -432,8 +432,10 @@ __global__ void __launch_bounds__(kStrip * GaussCfg<Q>::NT)
   const int32_t el = se[w];
   const bool live = el >= 0;
   const int64_t ee = live ? el : se[0];  // a slot past the strip's end works on a valid element
-  const bool has_prev = live && w > 0;
-  const bool has_next = (w + 1 < kStrip) && se[w < kStrip - 1 ? w + 1 : w] >= 0 && live;
+  // a group holds whole strips: bit w of its link byte says slot w + 1 continues slot w's strip
+  const uint32_t link = slink[s_begin + sl];
+  const bool has_prev = live && w > 0 && ((link >> (w > 0 ? w - 1 : 0)) & 1u);
+  const bool has_next = live && (w + 1 < kStrip) && ((link >> w) & 1u);
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
   const bool skip = has_prev && node_lane && a == 0;  // written by the previous element

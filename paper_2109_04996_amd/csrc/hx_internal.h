@@ -26,7 +26,7 @@ constexpr bool gauss_strips(int P, int Q, bool mass, int NC) {
   return mass ? P == 8 : (NC == 1 && Q == 8 && (P == 7 || P == 8));
 }
 constexpr bool strip_degree(int P) { return colloc_strips(P) || P == 7; }  // the mesh builds strips
-constexpr int kMinStripsPerColor = 512;  // collocated strips below P = 8: at least this many per color on average
+constexpr int kMinStripsPerColor = 512;  // collocated strips below P = 8: at least this many strip groups (workgroups) per color on average
 // elements per strip for P nodes per direction: seven for P = 3 (they fill one wavefront), else kStrip
 constexpr int strip_len(int P) { return P == 3 ? 7 : kStrip; }
 constexpr int kMaxQ = 10;  // quadrature points per direction
@@ -110,10 +110,12 @@ struct hx_mesh_s {
   // r1 = -1 face, scattered together by one workgroup of the collocated kernel. Strips have
   // their own coloring (no two strips of a color share a node) and ownership bits; element ids
   // are internal positions. Empty unless strip_degree(P) and the mesh has such chains.
+  // Whole strips of one color are packed into groups of up to strip_len(P) elements, one workgroup each.
   int nstrip_colors = 0;
-  int64_t nstrips = 0;
-  std::vector<int64_t> strip_color_start;  // nstrip_colors + 1, in strips
-  hx::DevBuf<int32_t> strip_elems;         // [nstrips][kStrip], -1 past the strip's end
+  int64_t nstrips = 0, nstrip_groups = 0;
+  std::vector<int64_t> strip_color_start;  // nstrip_colors + 1, in groups
+  hx::DevBuf<int32_t> strip_elems;         // [nstrip_groups][kStrip], -1 past the group's last element
+  hx::DevBuf<uint8_t> strip_link;          // [nstrip_groups] bit w: slot w + 1 continues slot w's strip
   hx::DevBuf<uint16_t> strip_own;          // [E_internal][P^2] bit k: first write of node (i,j,k) in strip order
   // transpose of the element restriction (made on first use): the E-vector slots e*P^3 + l (caller
   // element e, local node l) of each node, ascending; gather_ptr has nnodes + 1 entries

@@ -123,8 +123,8 @@ int greedy_color(int P3, int64_t nnodes, const int32_t *en, const std::vector<in
 // w's part), and ownership follows the strip order. Returns false (no strips) when the chains
 // are too short to pay off or the strips need more than 64 colors.
 bool build_strips(hx_mesh_s &m, const std::vector<int32_t> &idx, const std::vector<uint64_t> &mk_int,
-                  const std::vector<int64_t> &row_key_int, std::vector<int32_t> &selems, std::vector<uint16_t> &sown,
-                  std::string &err) {
+                  const std::vector<int64_t> &row_key_int, std::vector<int32_t> &selems, std::vector<uint8_t> &glink,
+                  std::vector<uint16_t> &sown, std::string &err) {
   const int P = m.P, P2 = P * P, P3 = P2 * P, p = P - 1;
   const int64_t E = m.nelem;
   std::unordered_map<int32_t, std::vector<int32_t>> by_origin;
@@ -249,6 +249,39 @@ bool build_strips(hx_mesh_s &m, const std::vector<int32_t> &idx, const std::vect
           }
     }
   }
+
+  // Pack whole strips of one color, in the color's order, into groups of at most strip_len(P)
+  // elements: one workgroup per group. Where chains are long (lattices) every group is one strip;
+  // where they are short (rotated or unstructured elements) a group holds several strips instead
+  // of one strip and idle slots. Strips of one color share no node, so the packing changes neither
+  // the ownership bits nor the results. Bit w of a group's link byte: slot w + 1 continues the
+  // strip of slot w.
+  const int SLen = hx::strip_len(P);
+  std::vector<int32_t> gel;
+  glink.clear();
+  std::vector<int64_t> gstart(ncol + 1, 0);
+  for (int c = 0; c < ncol; ++c) {
+    gstart[c] = (int64_t)glink.size();
+    int fill = SLen;  // no open group
+    for (int64_t t = m.strip_color_start[c]; t < m.strip_color_start[c + 1]; ++t) {
+      const int len = (int)strips[ord[t]].size();
+      if (fill + len > SLen) {
+        gel.insert(gel.end(), hx::kStrip, -1);
+        glink.push_back(0);
+        fill = 0;
+      }
+      int32_t *g = gel.data() + (glink.size() - 1) * hx::kStrip;
+      for (int w = 0; w < len; ++w) {
+        g[fill + w] = selems[(size_t)t * hx::kStrip + w];
+        if (w + 1 < len) glink.back() |= (uint8_t)(1u << (fill + w));
+      }
+      fill += len;
+    }
+  }
+  gstart[ncol] = (int64_t)glink.size();
+  selems.swap(gel);
+  m.strip_color_start = gstart;
+  m.nstrip_groups = (int64_t)glink.size();
   return true;
 }
 
@@ -453,6 +486,7 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
 
   // strips for the strip-scatter kernels
   std::vector<int32_t> selems;
+  std::vector<uint8_t> glink;
   std::vector<uint16_t> sown;
   bool strips = false;
   if (hx::strip_degree(P)) {
@@ -463,9 +497,10 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       for (int d = 0; d < 3; ++d) rk_int[t * 3 + d] = row_key[(int64_t)m->order[t] * 3 + d];
     }
     std::string serr;
-    strips = build_strips(*m, idx, mk_int, rk_int, selems, sown, serr);
+    strips = build_strips(*m, idx, mk_int, rk_int, selems, glink, sown, serr);
     if (!strips) {
       m->nstrips = 0;
+      m->nstrip_groups = 0;
       m->nstrip_colors = 0;
       m->strip_color_start.clear();
     }
@@ -487,6 +522,7 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       (e = m->freemask.upload(fm.data(), fm.size())) != hipSuccess ||
       (e = m->zeros.upload(std::vector<double>(64, 0.0).data(), 64)) != hipSuccess ||
       (strips && ((e = m->strip_elems.upload(selems.data(), selems.size())) != hipSuccess ||
+                  (e = m->strip_link.upload(glink.data(), glink.size())) != hipSuccess ||
                   (e = m->strip_own.upload(sown.data(), sown.size())) != hipSuccess))) {
     delete m;
     return hx::hip_fail(e, "mesh upload");
@@ -536,6 +572,7 @@ extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
     s->max_color = std::max<int64_t>(s->max_color, m->color_start[c + 1] - m->color_start[c]);
   s->nstrips = m->nstrips;
   s->nstrip_colors = m->nstrip_colors;
+  s->nstrip_groups = m->nstrip_groups;
   s->index_mode = m->idx_affine.ptr ? 2 : m->idx_rows.ptr ? 1 : 0;
   return HX_OK;
 }

@@ -47,8 +47,9 @@ struct StripCfg {
   static_assert(P2 <= 64, "an element's lines must fit one wavefront");
 };
 
-// One workgroup per (strip, component) of color [s_begin, s_begin + gridDim.x / NC); strip s's elements are
-// selems[s][0..len) (internal positions), -1 past the end. IDX: 0 one node id per element node,
+// One workgroup per (group, component) of color [s_begin, s_begin + gridDim.x / NC); group s holds one or
+// more whole strips of one color in selems[s][0..len) (internal positions), -1 past the end, and slink[s]
+// marks which neighbouring slots belong to one strip. IDX: 0 one node id per element node,
 // 1 one per r1-row (ROWS of k_colloc), 2 {base, s_j, s_k} per element, read with scalar loads
 // (node (i, j, k) = base + i + j s_j + k s_k), so the gather does not wait on a vector load.
 // sown: the strip-order ownership bits of each element.
@@ -58,8 +59,8 @@ template <int P, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(StripCfg<P>::NW * 64)
     k_colloc_strip(const int32_t *__restrict__ idx, const uint16_t *__restrict__ sown, const TQ *__restrict__ qd,
                    const T *__restrict__ Dg, const T *__restrict__ x, T *__restrict__ y,
-                   const int32_t *__restrict__ selems, int64_t s_begin, const T *__restrict__ zero,
-                   const TQ *__restrict__ qm = nullptr) {
+                   const int32_t *__restrict__ selems, const uint8_t *__restrict__ slink, int64_t s_begin,
+                   const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   using SC = StripCfg<P>;
   constexpr int P2 = P * P, P3 = P2 * P, LS = P + 1, PL = P * LS, BUF = P * PL, SL = SC::SL, EPW = SC::EPW;
   __shared__ T s0[SL][BUF];
@@ -84,8 +85,10 @@ __global__ void __launch_bounds__(StripCfg<P>::NW * 64)
   const int32_t el = se[w];
   const bool live = el >= 0 && lane_ok;
   const int64_t ee = el >= 0 ? el : se[0];  // a slot past the strip's end works on a valid element
-  const bool has_prev = live && w > 0;
-  const bool has_next = live && (w + 1 < SL) && se[w < SL - 1 ? w + 1 : w] >= 0;
+  // a group holds whole strips: bit w of its link byte says slot w + 1 continues slot w's strip
+  const uint32_t link = slink[s];
+  const bool has_prev = live && w > 0 && ((link >> (w > 0 ? w - 1 : 0)) & 1u);
+  const bool has_next = live && (w + 1 < SL) && ((link >> w) & 1u);
   // this lane's nodes are written by the previous element of the strip
   const bool skip = has_prev && a == 0;
   T *const S0 = s0[w];

@@ -37,7 +37,8 @@ class HexpaError(RuntimeError):
 class hx_mesh_stats(C.Structure):
     _fields_ = [("p", C.c_int), ("ncolors", C.c_int), ("nelem", C.c_int64), ("nnodes", C.c_int64),
                 ("nfree", C.c_int64), ("nuntouched", C.c_int64), ("max_color", C.c_int64),
-                ("nstrips", C.c_int64), ("nstrip_colors", C.c_int64), ("index_mode", C.c_int)]
+                ("nstrips", C.c_int64), ("nstrip_colors", C.c_int64), ("nstrip_groups", C.c_int64),
+                ("index_mode", C.c_int)]
 
 
 class hx_kappa_rff(C.Structure):

@@ -30,6 +30,9 @@ def test_strip_counts(p, N, nstrips):
         assert pr.stats["nstrips"] == nstrips
         if nstrips:
             assert pr.stats["nstrip_colors"] >= 2
+            # whole strips packed into groups of at most 8 (7 at p = 2) elements
+            sl = 7 if p == 2 else 8
+            assert -(-mesh["nelem"] // sl) <= pr.stats["nstrip_groups"] <= nstrips
 
 
 @pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
@@ -43,6 +46,8 @@ def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, p, q):
     A = fem.assemble(mesh, p, q, rule, kind)
     with Problem(N, p, q, rule, kind, ncomp=ncomp, mesh=mesh) as pr:
         assert 0 < pr.stats["nstrips"] < mesh["nelem"]
+        # short chains: workgroups hold several whole strips
+        assert 0 < pr.stats["nstrip_groups"] < pr.stats["nstrips"]
         x = uniform_vector(mesh["nnodes"], 7, ncomp)
         y = pr.apply(pr.to_dev(x)).cpu().numpy()
         yr = fem.apply(A, x, ncomp)
