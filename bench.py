@@ -178,6 +178,9 @@ def solves(pr, mass_pr, maxit=20000):
         "ir_fp32_jacobi": dict(mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_JACOBI, inner_qdata=hx.HX_FP32),
         "ir_fp32_cheb4": dict(mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32,
                               inner_qdata=hx.HX_FP32),
+        "mixed_fp32_jacobi": dict(mode=hx.HX_SOLVE_MIXED, inner_qdata=hx.HX_FP32),
+        "mixed_fp32_cheb4": dict(mode=hx.HX_SOLVE_MIXED, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32,
+                                 inner_qdata=hx.HX_FP32),
     }
     # p-multigrid V-cycle (degrees p, p/2, ..., 1) inside flexible CG
     mg, coarse, mg_setup = pmg_hierarchy(pr, "gll")
@@ -257,6 +260,9 @@ def suite_vector_ir(p=6, N=30):
     _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
     _, out["ir_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP64)
     _, out["ir_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP32)
+    # one FP32 PCG with FP64 residual replacement (reliable updates): the Krylov space is kept
+    _, out["mixed_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, inner_qdata=hx.HX_FP64)
+    _, out["mixed_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, inner_qdata=hx.HX_FP32)
     for name, prec in (("fp64_fcg_pmg", hx.HX_FP64), ("fp64_fcg_pmg_fp32", hx.HX_FP32)):
         mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", prec=prec)
         _, out[name] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)

@@ -255,11 +255,17 @@ enum { HX_PC_NONE = 0, HX_PC_JACOBI = 1, HX_PC_CHEBYSHEV = 2, HX_PC_MLP = 3, HX_
 
 /* p-multigrid hierarchy (declared below) */
 typedef struct hx_pmg_s *hx_pmg;
-enum { HX_SOLVE_FP64 = 0, HX_SOLVE_IR = 1 };
+enum { HX_SOLVE_FP64 = 0, HX_SOLVE_IR = 1, HX_SOLVE_MIXED = 2 };
 
 typedef struct {
   int mode;            /* HX_SOLVE_FP64: FP64 PCG. HX_SOLVE_IR: FP64 iterative
-                          refinement around an FP32 inner PCG                 */
+                          refinement around an FP32 inner PCG (each restart
+                          discards the Krylov space). HX_SOLVE_MIXED: one FP32
+                          PCG whose residual is replaced by the FP64 residual
+                          b - A x (x accumulated in FP64) whenever it has fallen
+                          by reliable_delta since the last replacement, keeping
+                          the search direction (reliable updates, van der Vorst
+                          and Ye 2000); converged on the FP64 residual        */
   int precond;         /* HX_PC_*                                            */
   double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 (free nodes) */
   int maxit;           /* iteration cap (outer cap for IR)                    */
@@ -276,7 +282,8 @@ typedef struct {
   int inner_maxit;     /* IR: inner iteration cap per outer step (a restart
                           loses the Krylov space: keep it above the iterations
                           one inner solve needs)                               */
-  int inner_qdata;     /* IR: HX_FP64 or HX_FP32 geometric factors            */
+  int inner_qdata;     /* IR and MIXED: HX_FP64 or HX_FP32 geometric factors of
+                          the FP32 operator                                    */
   int flexible;        /* 1: flexible CG (Polak-Ribiere beta) for preconditioners
                           that are not exactly linear or symmetric (the bf16
                           Chebyshev forms); 0: plain PCG                         */
@@ -314,6 +321,10 @@ typedef struct {
                           operator and its mesh. Results differ from
                           HX_SCATTER_COLORS in the last bits (summation order) and
                           are deterministic                                        */
+  double reliable_delta; /* HX_SOLVE_MIXED: replace the FP32 residual by the FP64
+                          one when its norm has fallen below reliable_delta
+                          times the norm at the last replacement (checked every
+                          check_every iterations), 0 < reliable_delta < 1     */
 } hx_solve_opts;
 
 enum { HX_SCATTER_COLORS = 0, HX_SCATTER_GATHER = 1 };
@@ -340,7 +351,7 @@ typedef struct {
  * check_every 10, degree 4, ratio 30, FP32 Chebyshev, 20 Lanczos steps,
  * inner_rtol 1e-4, inner_maxit 10000, FP64 inner qdata, flexible 0, no network,
  * fallback Jacobi, stall window 20 iterations, stall factor 0.1, mlp_mode 1,
- * graph 0, no hierarchy, HX_SCATTER_COLORS. */
+ * graph 0, no hierarchy, HX_SCATTER_COLORS, reliable_delta 0.25. */
 void hx_solve_opts_default(hx_solve_opts *opts);
 
 /* Solve A_II x_I = b_I with x = 0 on Dirichlet nodes (Benchmarks section:

@@ -580,10 +580,14 @@ hx_status cheb_apply_base(Ctx &c, const Cheb &ch, const Vecs<double> &v, const P
 // go through pc. Stops when r'r <= stop2, at maxit, or on breakdown.
 constexpr hx_status kStalled = -100;  // internal: the residual stopped falling (learned preconditioner)
 
+// Called at every host check with the recurrence r'r; may replace the residual (and r'z on the device)
+// and returns the r'r the loop goes on with.
+using CheckFn = std::function<hx_status(double rr, double *rr_next)>;
+
 template <typename T>
 hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, double rr0, double stop2, int maxit,
                    int check_every, bool flexible, int *iters, double *rr_out, int stall_window = 0,
-                   double stall_factor = 0.0) {
+                   double stall_factor = 0.0, const CheckFn *on_check = nullptr) {
   std::vector<std::pair<int, double>> hist;  // (iteration, r'r) at the host checks (stall check only)
   if (stall_window > 0) hist.emplace_back(0, rr0);
   HX_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * c.n, c.s));
@@ -699,6 +703,13 @@ hx_status pcg_core(Ctx &c, const Vecs<T> &v, const PrecFn<T> *pc, int op_prec, d
         *rr_out = rr;
         return fail(HX_EBREAKDOWN, "CG breakdown: p'Ap <= 0, r'z <= 0 or a non-finite scalar (flag " +
                                        std::to_string((int)c.hS[S_FLAG]) + ")");
+      }
+      if (on_check) {
+        if (hx_status st = (*on_check)(rr, &rr)) {
+          *iters = it;
+          *rr_out = rr;
+          return st;
+        }
       }
       if (stall_window > 0) {
         hist.emplace_back(it, rr);
@@ -971,13 +982,18 @@ extern "C" void hx_solve_opts_default(hx_solve_opts *o) {
   o->graph = 0;
   o->pmg = nullptr;
   o->scatter = HX_SCATTER_COLORS;
+  o->reliable_delta = 0.25;
 }
 
 extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx_solve_opts *opts,
                                   hx_solve_info *info, hx_stream stream) {
   if (!op || !b || !x || !opts || !info) return fail(HX_EINVAL, "null argument");
   const hx_solve_opts &o = *opts;
-  if (o.mode != HX_SOLVE_FP64 && o.mode != HX_SOLVE_IR) return fail(HX_EINVAL, "mode must be HX_SOLVE_FP64 or HX_SOLVE_IR");
+  if (o.mode != HX_SOLVE_FP64 && o.mode != HX_SOLVE_IR && o.mode != HX_SOLVE_MIXED)
+    return fail(HX_EINVAL, "mode must be HX_SOLVE_FP64, HX_SOLVE_IR or HX_SOLVE_MIXED");
+  const bool mixed = o.mode == HX_SOLVE_MIXED;
+  if (mixed && !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0))
+    return fail(HX_EINVAL, "HX_SOLVE_MIXED needs 0 < reliable_delta < 1");
   if (o.precond < HX_PC_NONE || o.precond > HX_PC_PMG) return fail(HX_EINVAL, "precond out of range");
   const bool pmg = o.precond == HX_PC_PMG;
   if (pmg && !o.pmg) return fail(HX_EINVAL, "HX_PC_PMG needs opts.pmg");
@@ -1005,10 +1021,10 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     return fail(HX_EINVAL, "cheb_prec must be HX_FP64, HX_FP32, HX_BF16 or HX_BF16_SPLIT");
   if (o.mode == HX_SOLVE_IR && (!(o.inner_rtol > 0 && o.inner_rtol < 1) || o.inner_maxit < 1))
     return fail(HX_EINVAL, "IR needs 0 < inner_rtol < 1 and inner_maxit >= 1");
-  if (o.mode == HX_SOLVE_IR && o.inner_qdata != HX_FP64 && o.inner_qdata != HX_FP32)
+  if ((o.mode == HX_SOLVE_IR || mixed) && o.inner_qdata != HX_FP64 && o.inner_qdata != HX_FP32)
     return fail(HX_EINVAL, "inner_qdata must be HX_FP64 or HX_FP32");
-  if (o.mode == HX_SOLVE_IR && cheb && o.cheb_prec == HX_FP64)
-    return fail(HX_EINVAL, "the IR inner solve runs in FP32: cheb_prec must be HX_FP32, HX_BF16 or HX_BF16_SPLIT");
+  if ((o.mode == HX_SOLVE_IR || mixed) && cheb && o.cheb_prec == HX_FP64)
+    return fail(HX_EINVAL, "the FP32 solve needs cheb_prec HX_FP32, HX_BF16 or HX_BF16_SPLIT");
   if (cheb && cheb_bf16 && (op->kind != HX_DIFFUSION || op->ncomp != 1))
     return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
   if (o.scatter != HX_SCATTER_COLORS && o.scatter != HX_SCATTER_GATHER)
@@ -1056,12 +1072,12 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   else LAUNCH_V((k_dinv<double, 3>), n, dg, op->mesh->freemask.ptr, v.dinv);
   HX_HIP(hipGetLastError());
 
-  const bool use32 = o.mode == HX_SOLVE_IR || (cheb && o.cheb_prec != HX_FP64);
+  const bool use32 = o.mode == HX_SOLVE_IR || mixed || (cheb && o.cheb_prec != HX_FP64);
   Vecs<float> v32{};
   if (use32) {
     if (hx_status st = carve(op->work32, n, v32)) return st;
     LAUNCH_V((k_convert<double, float>), n, 1.0, v.dinv, v32.dinv);
-    const bool q32 = (o.mode == HX_SOLVE_IR && o.inner_qdata == HX_FP32) || (cheb && o.cheb_prec == HX_FP32);
+    const bool q32 = ((o.mode == HX_SOLVE_IR || mixed) && o.inner_qdata == HX_FP32) || (cheb && o.cheb_prec == HX_FP32);
     if (q32)
       if (hx_status st = make_qdata32(*op, s)) return st;
     HX_HIP(hipGetLastError());
@@ -1182,6 +1198,58 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
       info->iterations += it2;
     }
     info->rel_residual = std::sqrt(rre) / bn;
+  } else if (mixed) {
+    // One FP32 PCG on A d = r0 with reliable updates: whenever the recurrence residual has fallen by
+    // reliable_delta since the last replacement (or below the target), the FP32 correction d is added
+    // to x in FP64, r = m (b - A x) is formed with the FP64 operator and replaces the FP32 residual,
+    // z and r'z are recomputed from it, and the search direction is kept, so the Krylov space built so
+    // far is not discarded as an iterative-refinement restart would. Convergence is decided on the
+    // FP64 residual.
+    // as in refinement: the Chebyshev polynomial's operator in cheb_prec, the CG operator on FP32
+    // vectors with the geometric factors inner_qdata names
+    const int inner_prec = cheb ? o.cheb_prec : o.inner_qdata;
+    const int op32 = (o.inner_qdata == HX_FP32) ? HX_FP32 : HX_FP64;
+    PrecFn<float> pcc = [&](const float *r, float *z) -> hx_status {
+      return cheb_apply<float>(c, ch, v32, r, z, inner_prec);
+    };
+    const double stop2 = o.rtol * o.rtol * bb;
+    const double d2 = o.reliable_delta * o.reliable_delta;
+    double rr_ref = rr;
+    int updates = 0;
+    LAUNCH_V((k_convert<double, float>), n, 1.0, v.r, v32.r);
+    CheckFn reliable = [&](double rr_s, double *rr_next) -> hx_status {
+      *rr_next = rr_s;
+      if (rr_s > std::max(stop2, d2 * rr_ref)) return HX_OK;
+      LAUNCH_V((k_axpy<float>), n, 1.0, v32.x, x);
+      HX_HIP(hipMemsetAsync(v32.x, 0, sizeof(float) * n, s));
+      if (hx_status st = apply_T(c, x, v.w, HX_FP64)) return st;
+      const uint8_t *fm = op->mesh->freemask.ptr;
+      if (NC == 1) LAUNCH_V((k_resid<float, double, 1>), n, 1.0, b, v.w, fm, v32.r, c.part1);
+      else LAUNCH_V((k_resid<float, double, 3>), n, 1.0, b, v.w, fm, v32.r, c.part1);
+      if (cheb) {
+        if (hx_status st = pcc(v32.r, v32.z)) return st;
+        LAUNCH_V((k_dot<float>), n, v32.r, v32.z, c.part0);
+      } else {
+        LAUNCH_V((k_jacobi<float>), n, v32.dinv, v32.r, v32.z, c.part0);
+      }
+      FINAL(c.part1, (const double *)nullptr, FIN_SUM, S_RR);
+      FINAL(c.part0, (const double *)nullptr, FIN_RZ, 0);
+      if (hx_status st = read_scalars(c)) return st;
+      ++updates;
+      rr_ref = c.hS[S_RR];
+      *rr_next = rr_ref;
+      if (c.hS[S_FLAG] != 0.0) return fail(HX_EBREAKDOWN, "r'z <= 0 or a non-finite scalar after a residual replacement");
+      return HX_OK;
+    };
+    int it = 0;
+    double rre = 0;
+    result = pcg_core<float>(c, v32, cheb ? &pcc : nullptr, op32, rr, stop2, o.maxit,
+                             o.check_every, o.flexible != 0, &it, &rre, 0, 0.0, &reliable);
+    LAUNCH_V((k_axpy<float>), n, 1.0, v32.x, x);  // the part since the last replacement
+    HX_HIP(hipGetLastError());
+    info->iterations = it;
+    info->outer_iterations = updates;
+    info->rel_residual = std::sqrt(rre) / bn;
   } else {
     // iterative refinement: FP64 residual, FP32 inner PCG on r / ||r||, FP64 update x += ||r|| d
     int outer = 0, inner_total = 0;
@@ -1228,7 +1296,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   double rr_true = 0;
   if (hx_status st = residual(&rr_true)) return st;
   info->true_rel_residual = std::sqrt(rr_true) / bn;
-  if (result == HX_OK && o.mode == HX_SOLVE_FP64 && info->rel_residual > o.rtol)
+  if (result == HX_OK && (o.mode == HX_SOLVE_FP64 || mixed) && info->rel_residual > o.rtol)
     result = fail(HX_ENOCONV, "PCG reached maxit without meeting rtol");
   return result;
 }

@@ -21,7 +21,7 @@ HX_GAUSS, HX_GLL = 0, 1
 HX_MASS, HX_DIFFUSION, HX_HELMHOLTZ = 0, 1, 2
 HX_FP64, HX_FP32, HX_BF16, HX_BF16_SPLIT = 0, 1, 2, 3
 HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP, HX_PC_PMG = 0, 1, 2, 3, 4
-HX_SOLVE_FP64, HX_SOLVE_IR = 0, 1
+HX_SOLVE_FP64, HX_SOLVE_IR, HX_SOLVE_MIXED = 0, 1, 2
 HX_SCATTER_COLORS, HX_SCATTER_GATHER = 0, 1
 
 STATUS_NAMES = {0: "HX_OK", -1: "HX_EINVAL", -2: "HX_ERANGE", -3: "HX_EUNSUPPORTED", -4: "HX_EGEOM",
@@ -59,7 +59,7 @@ class hx_solve_opts(C.Structure):
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("inner_qdata", C.c_int),
                 ("flexible", C.c_int), ("mlp", C.c_void_p), ("fallback", C.c_int), ("stall_window", C.c_int),
                 ("stall_factor", C.c_double), ("mlp_mode", C.c_int), ("graph", C.c_int), ("pmg", C.c_void_p),
-                ("scatter", C.c_int)]
+                ("scatter", C.c_int), ("reliable_delta", C.c_double)]
 
 
 class hx_pmg_opts(C.Structure):

@@ -96,6 +96,34 @@ def test_iterative_refinement(precond, qd):
         assert np.linalg.norm(x.cpu().numpy() - xd) <= 10 * np.linalg.norm(xo - xd) + 1e-12
 
 
+@pytest.mark.parametrize("ncomp,precond,qd,check", [(1, hx.HX_PC_JACOBI, hx.HX_FP64, 5), (1, hx.HX_PC_JACOBI, hx.HX_FP32, 1),
+                                                    (3, hx.HX_PC_JACOBI, hx.HX_FP32, 10),
+                                                    (1, hx.HX_PC_CHEBYSHEV, hx.HX_FP32, 2)])
+def test_mixed_reliable_updates(ncomp, precond, qd, check):
+    """FP32 PCG with FP64 residual replacement: meets the FP64 true residual, keeps the Krylov space
+    (iterations close to FP64 PCG's, not the restart count of refinement), and its error is that of a
+    plain FP64 solve at the same residual."""
+    mesh, pr, b, A, bo, free = _setup(4, 5, 7, "gauss", ncomp=ncomp, warp="B")
+    with pr:
+        opts = dict(precond=precond, cheb_prec=hx.HX_FP32, rtol=1e-8, check_every=check)
+        x64, i64 = pr.solve(b, **opts)
+        x, info = pr.solve(b, mode=hx.HX_SOLVE_MIXED, inner_qdata=qd, **opts)
+        assert info["true_rel_residual"] <= 1.05e-8, info
+        # one replacement per decade of residual (reliable_delta 0.1), at least
+        assert info["outer_iterations"] >= 4, info
+        assert info["iterations"] <= 1.15 * i64["iterations"] + 2 * check, (info, i64)
+        xd = solvers.direct_solve(A, bo, free)
+        xo, _, _ = solvers.jacobi_pcg(A, bo, free, tol=1e-8)
+        assert np.linalg.norm(x.cpu().numpy() - xd) <= 10 * np.linalg.norm(xo - xd) + 1e-12
+        assert np.all(x.cpu().numpy()[~free] == 0)
+        # a tight solve reaches the direct solution: the replacement leaves no FP32 floor
+        x2, info2 = pr.solve(b, mode=hx.HX_SOLVE_MIXED, inner_qdata=qd, **dict(opts, rtol=1e-12))
+        assert info2["true_rel_residual"] <= 1.05e-12, info2
+        assert np.linalg.norm(x2.cpu().numpy() - xd) <= 1e-9 * np.linalg.norm(xd)
+        with pytest.raises(hx.HexpaError):
+            pr.solve(b, mode=hx.HX_SOLVE_MIXED, reliable_delta=1.0)
+
+
 def test_failures_reported():
     mesh, pr, b, A, bo, free = _setup(3, 3, 5, "gauss")
     with pr:
