@@ -1,10 +1,13 @@
 """Throughput of the fused BP5 diffusion apply (p=7, q=8 GLL-collocated, FP64) on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 48] [--p 7] [--no-solves] [--no-cpu-baseline]
+                [--no-extra-lines] [--no-suites]
 
 A step is one operator apply y = A x over the whole L-vector (all element colors), inputs resident in
-HBM. Prints one JSON line with the metric, the roofline object of the apply kernel, the oracle CPU
-baseline, and time-to-1e-8 PCG solves on the same mesh.
+HBM. Prints one JSON line with the metric, the roofline object of the apply kernel (with the general
+index path beside it), the BP6 and Helmholtz apply lines, time-to-1e-8 solves on the same mesh and
+across the other workloads (3-component p = 5..8, the variable-coefficient p = 6 problem, the learned
+preconditioner), and the oracle CPU baseline.
 """
 from __future__ import annotations
 
@@ -188,7 +191,8 @@ def solves(pr, mass_pr, maxit=20000):
     # the same V-cycle in FP32 (vectors, operators with FP32 geometric factors, smoothers) in the FP64 FCG
     mg32, coarse32, mg32_setup = pmg_hierarchy(pr, "gll", prec=hx.HX_FP32)
     forms["fp64_fcg_pmg_fp32"] = dict(precond=hx.HX_PC_PMG, pmg=mg32.value)
-    ref = None
+    # every form's difference is taken against an FP64 solve to 1e-12 (the p-multigrid FCG)
+    ref = pr.solve(b, rtol=1e-12, maxit=2000, check_every=1, precond=hx.HX_PC_PMG, pmg=mg.value)[0].clone()
     for name, o in forms.items():
         print(f"[bench] solve {name}", file=sys.stderr, flush=True)
         x = pr.zeros()
@@ -200,13 +204,11 @@ def solves(pr, mass_pr, maxit=20000):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         xs = x.double()
-        if ref is None:
-            ref = xs.clone()
         out[name] = dict(status=info["status"], iterations=info["iterations"],
                          outer=info["outer_iterations"], applies=info["operator_applies"],
                          seconds=round(info["solve_seconds"], 4), setup_seconds=round(info["setup_seconds"], 4),
                          wall_seconds=round(wall, 4), true_rel_residual=info["true_rel_residual"],
-                         rel_diff_vs_fp64=float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)),
+                         rel_error_vs_fp64_reference=float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)),
                          # discretisation error: max-norm against u = sin sin sin at the nodes
                          err_vs_exact=float((xs - u_dev).abs().max() / u_dev.abs().max()),
                          gdofs_per_iteration=round(pr.n * info["iterations"] / max(info["solve_seconds"], 1e-9) / 1e9,
@@ -216,7 +218,8 @@ def solves(pr, mass_pr, maxit=20000):
     out["fp64_fcg_pmg_fp32"].update(degrees=pmg_degrees(pr.p), hierarchy_setup_seconds=round(mg32_setup, 3))
     pmg_close(mg, coarse)
     pmg_close(mg32, coarse32)
-    return out
+    out["reference"] = "FP64 flexible CG with the FP64 p-multigrid V-cycle to 1e-12"
+    return _speedups(out)
 
 
 def _timed_solve(pr, b, ref=None, **o):
@@ -239,14 +242,56 @@ def _timed_solve(pr, b, ref=None, **o):
     return x, rec
 
 
+def reference_solution(pr, b, rule, kappa=None):
+    """FP64 solution to a 1e-12 relative residual (flexible CG with the FP64 p-multigrid V-cycle), against
+    which every form's error is reported."""
+    mg, coarse, _ = pmg_hierarchy(pr, rule, kappa=kappa)
+    ref, info = pr.solve(b, rtol=1e-12, maxit=2000, check_every=1, precond=pmg_precond(), pmg=mg.value)
+    pmg_close(mg, coarse)
+    if info["status"] != "HX_OK":
+        raise RuntimeError(f"reference solve: {info}")
+    return ref
+
+
+def pmg_precond():
+    from paper_2109_04996_amd import hexpa as hx
+    return hx.HX_PC_PMG
+
+
+def _speedups(out, base="fp64_jacobi"):
+    """time of the plain FP64 Jacobi-PCG solve / time of each form (the solve, setup apart), and the same
+    counting each form's own setup (Lanczos estimate, diagonal, p-multigrid hierarchy)."""
+    t0 = out[base]["seconds"]
+    for k, v in out.items():
+        if isinstance(v, dict) and "seconds" in v and v.get("status") == "HX_OK":
+            v["vs_fp64_jacobi"] = round(t0 / max(v["seconds"], 1e-9), 3)
+            setup = v.get("hierarchy_setup_seconds", 0.0) + v.get("setup_seconds", 0.0)
+            v["vs_fp64_jacobi_with_setup"] = round((t0 + out[base].get("setup_seconds", 0.0))
+                                                   / max(v["seconds"] + setup, 1e-9), 3)
+    return out
+
+
+def _pmg_form(pr, b, ref, rule, out, name, kappa=None, **pmg_opts):
+    from paper_2109_04996_amd import hexpa as hx
+    mg, coarse, mg_setup = pmg_hierarchy(pr, rule, kappa=kappa, **pmg_opts)
+    _, out[name] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+    out[name].update(degrees=pmg_degrees(pr.p), hierarchy_setup_seconds=round(mg_setup, 3))
+    pmg_close(mg, coarse)
+
+
+VECTOR_CASES = ((5, 30), (6, 30), (7, 26), (8, 22))  # (p, N): 3.4M to 6.1M nodes x 3 components
+
+
 def suite_vector_ir(p=6, N=30):
-    """Vector diffusion, 3 interleaved components, q = p+2 Gauss, FP64 PCG vs FP32-operator IR."""
+    """Vector diffusion, 3 interleaved components, q = p+2 Gauss: plain FP64 PCG against the FP32-operator
+    forms (refinement, one FP32 CG with FP64 residual replacement, FP32 Chebyshev in FP64 CG) and the
+    p-multigrid V-cycle."""
     import numpy as np
 
     from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd.inputs import lattice_mesh
     from paper_2109_04996_amd.problem import Problem
-    print(f"[bench] vector IR suite p={p} N={N}", file=sys.stderr, flush=True)
+    print(f"[bench] vector suite p={p} N={N}", file=sys.stderr, flush=True)
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
     pr = Problem(N, p, p + 2, "gauss", "diffusion", ncomp=3, mesh=mesh)
     mass = Problem(N, p, p + 2, "gauss", "mass", ncomp=3, mesh=mesh)
@@ -254,26 +299,24 @@ def suite_vector_ir(p=6, N=30):
     f = 3 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
     b = mass.apply(pr.to_dev((f[:, None] * np.array([1.0, -1.0, 0.5])[None, :]).ravel()))
     mass.close()
-    ref, _ = pr.solve(b, rtol=1e-12, maxit=100000, check_every=50)
+    ref = reference_solution(pr, b, "gauss")
     out = dict(workload=f"BP4-type vector diffusion, 3 components, p={p}, q={p + 2} Gauss, mesh A {N}^3, "
-                        f"{mesh['nnodes']} nodes x 3, rtol 1e-8; reference: FP64 PCG to 1e-12")
+                        f"{mesh['nnodes']} nodes x 3, rtol 1e-8; reference: FP64 solve to 1e-12")
     _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
-    _, out["ir_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP64)
     _, out["ir_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, inner_qdata=hx.HX_FP32)
     # one FP32 PCG with FP64 residual replacement (reliable updates): the Krylov space is kept
-    _, out["mixed_fp32op_fp64qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, inner_qdata=hx.HX_FP64)
     _, out["mixed_fp32op_fp32qdata"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, inner_qdata=hx.HX_FP32)
-    for name, prec in (("fp64_fcg_pmg", hx.HX_FP64), ("fp64_fcg_pmg_fp32", hx.HX_FP32)):
-        mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", prec=prec)
-        _, out[name] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
-        out[name].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
-        pmg_close(mg, coarse)
+    _, out["fp64_cg_cheb4_fp32op"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32)
+    _, out["mixed_cheb4_fp32op"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, precond=hx.HX_PC_CHEBYSHEV,
+                                                cheb_prec=hx.HX_FP32, inner_qdata=hx.HX_FP32)
+    _pmg_form(pr, b, ref, "gauss", out, "fp64_fcg_pmg_fp32", prec=hx.HX_FP32)
     pr.close()
-    return out
+    return _speedups(out)
 
 
 def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
-    """Scalar variable-coefficient diffusion, p=6, q=8: FP64 PCG vs FP32/bf16-matrix-core Chebyshev forms."""
+    """Scalar variable-coefficient diffusion, p=6, q=8: FP64 PCG vs FP32/bf16-matrix-core Chebyshev forms and
+    the p-multigrid V-cycle."""
     from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd import learned
     from paper_2109_04996_amd.inputs import kappa_field_params
@@ -281,41 +324,30 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     t0 = time.perf_counter()
     pr, b = learned.problem_with_kappa(N, p, p + 2, "gauss", kappa_seed)
     setup = time.perf_counter() - t0
-    ref, _ = pr.solve(b, rtol=1e-12, maxit=100000, check_every=50)
+    kp = kappa_field_params(kappa_seed, M=512)
+    ref = reference_solution(pr, b, "gauss", kappa=kp)
     out = dict(workload=f"diffusion with kappa = exp(g), g a seeded random-Fourier-feature field (seed {kappa_seed}, "
                         f"contrast ~1e2), p={p}, q={p + 2} Gauss, mesh A {N}^3, {pr.mesh['nnodes']} DOFs, b = B 1, "
-                        f"rtol 1e-8; reference: FP64 PCG to 1e-12", setup_seconds=round(setup, 2))
+                        f"rtol 1e-8; reference: FP64 solve to 1e-12", problem_setup_seconds=round(setup, 2))
     _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
     _, out["fp64_cg_cheb4_fp32op"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_FP32)
-    _, out["fp64_fcg_cheb4_bf16mfma"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV, cheb_prec=hx.HX_BF16,
-                                                     flexible=1)
+    # the literal form: FP64 refinement, FP32 operator, Chebyshev(4) on the bf16 matrix cores
     _, out["ir_fp32op_cheb4_bf16mfma"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
                                                       cheb_prec=hx.HX_BF16, inner_qdata=hx.HX_FP32, flexible=1)
     # the same matrix cores with hi + lo bfloat16 operands
-    _, out["fp64_fcg_cheb4_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV,
-                                                      cheb_prec=hx.HX_BF16_SPLIT, flexible=1)
     _, out["fp64_cg_cheb4_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_CHEBYSHEV,
                                                      cheb_prec=hx.HX_BF16_SPLIT, flexible=0)
     _, out["ir_fp32op_cheb4_bf16split"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_IR, precond=hx.HX_PC_CHEBYSHEV,
                                                        cheb_prec=hx.HX_BF16_SPLIT, inner_qdata=hx.HX_FP32,
                                                        flexible=1)
-    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512))
-    _, out["fp64_fcg_pmg"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
-    out["fp64_fcg_pmg"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
-    pmg_close(mg, coarse)
-    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512),
-                                         prec=hx.HX_FP32)
-    _, out["fp64_fcg_pmg_fp32"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
-    out["fp64_fcg_pmg_fp32"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
-    pmg_close(mg, coarse)
+    _, out["mixed_cheb4_bf16split"] = _timed_solve(pr, b, ref, mode=hx.HX_SOLVE_MIXED, precond=hx.HX_PC_CHEBYSHEV,
+                                                   cheb_prec=hx.HX_BF16_SPLIT, inner_qdata=hx.HX_FP32, flexible=1)
+    _pmg_form(pr, b, ref, "gauss", out, "fp64_fcg_pmg", kappa=kp)
+    _pmg_form(pr, b, ref, "gauss", out, "fp64_fcg_pmg_fp32", kappa=kp, prec=hx.HX_FP32)
     # the FP32 hierarchy with the finest level's operator on the matrix cores (hi + lo bf16 operands)
-    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(kappa_seed, M=512),
-                                         prec=hx.HX_BF16_SPLIT)
-    _, out["fp64_fcg_pmg_bf16split"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
-    out["fp64_fcg_pmg_bf16split"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
-    pmg_close(mg, coarse)
+    _pmg_form(pr, b, ref, "gauss", out, "fp64_fcg_pmg_bf16split", kappa=kp, prec=hx.HX_BF16_SPLIT)
     pr.close()
-    return out
+    return _speedups(out)
 
 
 def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 1003), eval_seed=100):
@@ -614,8 +646,10 @@ def main():
     ap.add_argument("--no-extra-lines", action="store_true",
                     help="skip the general-index-path, BP6 vector and Helmholtz apply lines")
     ap.add_argument("--copy-probe", action="store_true", help="(the copy probe always runs; kept for old commands)")
-    ap.add_argument("--all", action="store_true",
-                    help="also run the vector-IR, variable-coefficient Chebyshev and learned-preconditioner suites")
+    ap.add_argument("--no-suites", action="store_true",
+                    help="skip the time-to-solution suites (vector p = 5..8, variable coefficient, learned)")
+    ap.add_argument("--all", action="store_true", help="(the suites always run unless --no-suites; kept for old "
+                                                       "commands)")
     ap.add_argument("--sweep", action="store_true",
                     help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
     ap.add_argument("--pmc-run", action="store_true",
@@ -789,13 +823,21 @@ def main():
     del x, y
     if not a.no_extra_lines:
         extra_lines(out, mesh, N, p, roof)
-    if a.all:
-        torch.cuda.empty_cache()
-        out["vector_ir"] = suite_vector_ir()
-        torch.cuda.empty_cache()
-        out["kappa_chebyshev"] = suite_kappa_cheb()
-        torch.cuda.empty_cache()
-        out["learned"] = suite_learned()
+    if not a.no_suites:
+        # time-to-1e-8 across the workloads: vector problems p = 5..8, the variable-coefficient problem, the
+        # learned preconditioner; a suite that fails records its error instead of ending the run
+        def run(name, fn, *args):
+            torch.cuda.empty_cache()
+            t0 = time.perf_counter()
+            try:
+                res = fn(*args)
+            except Exception as e:  # noqa: BLE001 - reported in the line
+                res = dict(error=f"{type(e).__name__}: {e}")
+            res["suite_wall_seconds"] = round(time.perf_counter() - t0, 1)
+            return res
+        out["vector"] = {f"p{pv}": run("vector", suite_vector_ir, pv, Nv) for pv, Nv in VECTOR_CASES}
+        out["kappa_chebyshev"] = run("kappa", suite_kappa_cheb)
+        out["learned"] = run("learned", suite_learned)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
