@@ -12,7 +12,8 @@ nor the coarse solver. The readings taken here:
   the restriction is its transpose;
 * smoother: Chebyshev acceleration of D^-1 A (``solvers.chebyshev_apply``),
   ``degree`` steps, before and after the coarse correction, on the interval
-  [lam_hi / ratio, lam_hi];
+  [lam_hi / ratio, lam_hi]; a level may replace D^-1 by another base map M
+  (the learned element map), with lam_max that of M A;
 * coarsest level: Jacobi-PCG (``solvers.jacobi_pcg``), to a relative tolerance
   or, with tolerance 0, for exactly ``coarse_maxit`` iterations.
 
@@ -66,9 +67,12 @@ def prolongation(mesh_f: dict, mesh_c: dict, p_fine: int, p_coarse: int) -> sp.c
 
 
 class Level:
-    """One level: its assembled operator, free mask, Chebyshev interval and the prolongation from the next level."""
+    """One level: its assembled operator, free mask, Chebyshev interval and the prolongation from the next level.
 
-    def __init__(self, A: sp.csr_matrix, free: np.ndarray, lam_max: float = 0.0, P: sp.csr_matrix | None = None):
+    ``base``: the smoother's base map v -> M v (default: D^-1 of the level); lam_max is then that of M A."""
+
+    def __init__(self, A: sp.csr_matrix, free: np.ndarray, lam_max: float = 0.0, P: sp.csr_matrix | None = None,
+                 base=None):
         self.free = free
         self.f = free.astype(float)
         self.A_full = A
@@ -76,6 +80,7 @@ class Level:
         self.dinv = np.where(free, 1.0 / A.diagonal(), 0.0)
         self.lam_max = lam_max
         self.P = P
+        self.base = base
 
 
 def vcycle(levels: list, r: np.ndarray, degree: int = 2, ratio: float = 10.0, coarse_rtol: float = 0.0,
@@ -94,13 +99,14 @@ def vcycle(levels: list, r: np.ndarray, degree: int = 2, ratio: float = 10.0, co
         return x
     lam_hi = 1.1 * lv.lam_max
     lam_lo = lam_hi / ratio
-    x = chebyshev_apply(lv.A, lv.dinv, r, lam_lo, lam_hi, degree)  # pre-smoothing from 0
+    M = lv.dinv if lv.base is None else lv.base
+    x = chebyshev_apply(lv.A, M, r, lam_lo, lam_hi, degree)  # pre-smoothing from 0
     t = (r - lv.A @ x) * lv.f
     rc = lv.P.T @ t
     ec = vcycle(levels, rc, degree, ratio, coarse_rtol, coarse_maxit, coarse, l + 1)
     x = x + (lv.P @ ec) * lv.f  # coarse correction
     t = (r - lv.A @ x) * lv.f
-    return x + chebyshev_apply(lv.A, lv.dinv, t, lam_lo, lam_hi, degree)  # post-smoothing
+    return x + chebyshev_apply(lv.A, M, t, lam_lo, lam_hi, degree)  # post-smoothing
 
 
 def flexible_pcg(A: sp.csr_matrix, b: np.ndarray, free: np.ndarray, precond, tol: float = 1e-8,

@@ -75,18 +75,21 @@ def chebyshev_apply(A: sp.csr_matrix, dinv: np.ndarray, r: np.ndarray, lam_lo: f
     """z = s(D^-1 A) D^-1 r by the three-term Chebyshev recurrence, ``degree`` steps from z = 0.
 
     Uses degree-1 operator applies. ``dinv`` is zero on constrained nodes, so
-    z stays zero there.
+    z stays zero there. ``dinv`` may instead be a map v -> M v (a base other
+    than the diagonal, such as the learned element map): the same recurrence
+    then gives z = s(M A) M r.
     """
+    M = dinv if callable(dinv) else (lambda v: dinv * v)
     theta = 0.5 * (lam_hi + lam_lo)
     delta = 0.5 * (lam_hi - lam_lo)
     sigma = theta / delta
     rho = 1.0 / sigma
-    d = dinv * r / theta
+    d = M(r) / theta
     z = d.copy()
     for _ in range(degree - 1):
         res = r - A @ z
         rho_new = 1.0 / (2.0 * sigma - rho)
-        d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * res)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * M(res)
         z = z + d
         rho = rho_new
     return z

@@ -3,8 +3,8 @@
 A copy of ``oracle/`` is written to a temporary package with one edit (a
 transposed inverse Jacobian, a dropped determinant, a wrong sign, swapped
 derivative tables, a wrong quadrature weight, a wrong Chebyshev coefficient,
-a wrong multigrid correction sign, a dropped post-smoothing, wrong
-interpolation points),
+a Chebyshev base map ignored, a wrong multigrid correction sign, a dropped
+post-smoothing, wrong interpolation points),
 and the pin tests are run against it with the module swapped in. Every
 mutant must make at least one pin fail.
 """
@@ -32,10 +32,12 @@ MUTANTS = {
     "lambda_max_unscaled": ("solvers.py", "S = sp.diags(s) @ Aii @ sp.diags(s)", "S = Aii"),
     "helmholtz_mass_scale": ("fem.py", "return (alpha * A + beta * B).tocsr()", "return (alpha * A + alpha * B).tocsr()"),
     "gll_weight_formula": ("quadrature.py", "w = 2.0 / (p * (p + 1) * Pp * Pp)", "w = 2.0 / (p * (p + 1) * Pp)"),
-    "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * res)",
-                              "d = rho_new * d + (2.0 * rho_new / delta) * (dinv * res)"),
+    "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * M(res)",
+                              "d = rho_new * d + (2.0 * rho_new / delta) * M(res)"),
+    "chebyshev_base_map_ignored": ("solvers.py", "M = dinv if callable(dinv) else (lambda v: dinv * v)",
+                                   "M = (lambda v: v) if callable(dinv) else (lambda v: dinv * v)"),
     "coarse_correction_sign": ("pmg.py", "x = x + (lv.P @ ec) * lv.f", "x = x - (lv.P @ ec) * lv.f"),
-    "dropped_post_smoothing": ("pmg.py", "return x + chebyshev_apply(lv.A, lv.dinv, t, lam_lo, lam_hi, degree)",
+    "dropped_post_smoothing": ("pmg.py", "return x + chebyshev_apply(lv.A, M, t, lam_lo, lam_hi, degree)",
                                "return x"),
     "interpolation_swapped_nodes": ("pmg.py", "return lagrange_table(xc, xf)", "return lagrange_table(xc, -xf[::-1] ** 3)"),
 }
@@ -46,7 +48,7 @@ PINS = {
                                    "test_kappa_location_closed_form", "test_helmholtz_forms"]),
     "quadrature.py": ("test_oracle_quadrature", ["test_closed_forms", "test_exactness_degrees"]),
     "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial",
-                                           "test_lambda_max_lanczos_branch"]),
+                                           "test_chebyshev_general_base_map", "test_lambda_max_lanczos_branch"]),
     "pmg.py": ("test_oracle_pmg", ["test_interpolation_1d", "test_prolongation_reproduces_coarse_space",
                                    "test_galerkin_identity", "test_vcycle_symmetric_and_contracting"]),
 }

@@ -65,6 +65,49 @@ def test_chebyshev_recurrence_equals_polynomial(k):
     np.testing.assert_allclose(z, zr, rtol=1e-10, atol=1e-12 * np.abs(zr).max())
 
 
+def test_chebyshev_general_base_map():
+    # the recurrence with a base map v -> M v in place of D^-1 (the learned smoother's form):
+    # (a) M = D^-1 as a map gives the array path bit for bit;
+    # (b) M a general SPD matrix on the free nodes (not diagonal): z = M^1/2 V s(L) V^T M^1/2 r with
+    #     (L, V) the eigenpairs of M^1/2 A M^1/2, s(l) = (1 - T_k(theta(l)) / T_k(theta(0))) / l;
+    # (c) M = A^-1 on the free nodes: z = s(1) A^-1 r.
+    mesh, A, b, free = _problem(N=3, p=2)
+    f = free.astype(float)
+    Am = (A.multiply(np.outer(f, f))).tocsr()
+    dinv = np.where(free, 1.0 / A.diagonal(), 0.0)
+    r = np.random.default_rng(4).standard_normal(b.size) * f
+    lmax = solvers.jacobi_lambda_max(A, free)
+    lo, hi = lmax * 1.1 / 30, lmax * 1.1
+    k = 4
+    np.testing.assert_array_equal(solvers.chebyshev_apply(Am, lambda v: dinv * v, r, lo, hi, k),
+                                  solvers.chebyshev_apply(Am, dinv, r, lo, hi, k))
+    nf = int(free.sum())
+    Aii = A[free][:, free].toarray()
+    G = np.random.default_rng(5).standard_normal((nf, nf)) / np.sqrt(nf)
+    Mf = np.diag(dinv[free]) + 0.02 * (G @ G.T) * dinv[free].mean()  # SPD, far from diagonal
+    M = lambda v: _embed(Mf @ v[free], free)
+    w, U = np.linalg.eigh(Mf)
+    Mh = (U * np.sqrt(w)) @ U.T
+    lam, V = np.linalg.eigh(Mh @ Aii @ Mh)
+    lo2, hi2 = lam.max() * 1.1 / 30, lam.max() * 1.1
+    th = lambda l: (hi2 + lo2 - 2 * l) / (hi2 - lo2)
+    Tk = lambda t: C.chebval(t, [0] * k + [1])
+    sv = (1 - Tk(th(lam)) / Tk(th(0.0))) / lam
+    zr = _embed(Mh @ (V @ (sv * (V.T @ (Mh @ r[free])))), free)
+    z = solvers.chebyshev_apply(Am, M, r, lo2, hi2, k)
+    np.testing.assert_allclose(z, zr, rtol=1e-9, atol=1e-11 * np.abs(zr).max())
+    Ainv = np.linalg.inv(Aii)
+    z = solvers.chebyshev_apply(Am, lambda v: _embed(Ainv @ v[free], free), r, lo, hi, k)
+    s1 = 1 - Tk((hi + lo - 2.0) / (hi - lo)) / Tk((hi + lo) / (hi - lo))
+    np.testing.assert_allclose(z, s1 * _embed(Ainv @ r[free], free), rtol=1e-10, atol=1e-12 * np.abs(z).max())
+
+
+def _embed(vf, free):
+    out = np.zeros(free.size)
+    out[free] = vf
+    return out
+
+
 def test_chebyshev_is_spd_and_pcg_converges():
     mesh, A, b, free = _problem(N=3, p=3)
     lmax = solvers.jacobi_lambda_max(A, free)
