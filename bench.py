@@ -350,11 +350,17 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     return _speedups(out)
 
 
-def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 1003), eval_seed=100):
-    """Learned element preconditioner: training cost, then FCG with the network (alone and as the
-    base of a Chebyshev polynomial) against Jacobi and Chebyshev PCG on a held-out field."""
+LEARNED_CASES = ((4, 43), (5, 35), (6, 29), (7, 25))  # (p, N_eval): 5.2M to 5.5M DOFs
+
+
+def suite_learned(p=5, N_eval=35, N_train=12, train_seeds=(1000, 1001, 1002, 1003), eval_seed=100):
+    """Learned element preconditioner at one degree: training cost, then FCG with the network (alone and as
+    the base of a Chebyshev polynomial) against Jacobi and Chebyshev PCG, and the p-multigrid V-cycle with
+    the network as its finest smoother's base against the same V-cycle with Jacobi-Chebyshev smoothing, on
+    a held-out coefficient field."""
     from paper_2109_04996_amd import hexpa as hx
     from paper_2109_04996_amd import learned
+    from paper_2109_04996_amd.inputs import kappa_field_params
     print(f"[bench] learned suite p={p}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     X, T = learned.training_set(p, p + 2, "gauss", N_train, train_seeds, groups_per_field=6, mode=1)
@@ -364,12 +370,14 @@ def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 100
           file=sys.stderr, flush=True)
     pr, b = learned.problem_with_kappa(N_eval, p, p + 2, "gauss", eval_seed)
     res = learned.compare_solves(pr, b, net)
-    # the stronger non-learned baseline: p-multigrid (degrees p, p/2, ..., 1) in flexible CG
-    from paper_2109_04996_amd.inputs import kappa_field_params
-    mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kappa_field_params(eval_seed, M=512))
-    _, res["pmg"] = _timed_solve(pr, b, None, precond=hx.HX_PC_PMG, pmg=mg.value)
-    res["pmg"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
-    pmg_close(mg, coarse)
+    # the stronger non-learned baseline: p-multigrid (degrees p, p/2, ..., 1) in flexible CG, and the same
+    # V-cycle with the learned map as the base of its finest smoother
+    kp = kappa_field_params(eval_seed, M=512)
+    for name, extra in (("pmg", {}), ("pmg_learned_smoother", dict(smoother_mlp=net.value))):
+        mg, coarse, mg_setup = pmg_hierarchy(pr, "gauss", kappa=kp, **extra)
+        _, res[name] = _timed_solve(pr, b, None, precond=hx.HX_PC_PMG, pmg=mg.value)
+        res[name].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup, 3))
+        pmg_close(mg, coarse)
     out = dict(workload=f"diffusion with kappa (held-out seed {eval_seed}), p={p}, q={p + 2} Gauss, mesh A "
                         f"{N_eval}^3, {pr.mesh['nnodes']} DOFs, b = B 1, rtol 1e-8",
                training=dict(rows=int(X.shape[0]), data_seconds=round(t_data, 2),
@@ -379,12 +387,16 @@ def suite_learned(p=5, N_train=16, N_eval=40, train_seeds=(1000, 1001, 1002, 100
                                             "exact element-patch solves of Jacobi-PCG residuals"),
                **res)
     t = {k: v["seconds"] for k, v in res.items()}
-    # each learned form against its own fallback, and against plain FP64 Jacobi PCG
+    # each learned form against its own fallback, against plain FP64 Jacobi PCG and against p-multigrid
     out["gain"] = dict(learned_vs_jacobi=round(t["jacobi"] / max(t["learned"], 1e-9), 3),
                        learned_cheb4_vs_chebyshev4=round(t["chebyshev4"] / max(t["learned_cheb4"], 1e-9), 3),
                        learned_cheb4_vs_jacobi=round(t["jacobi"] / max(t["learned_cheb4"], 1e-9), 3),
-                       best_learned_vs_pmg=round(t["pmg"] / max(min(t["learned"], t["learned_cheb4"]), 1e-9), 3))
-    best_learned = min(t["learned"], t["learned_cheb4"])
+                       learned_smoother_vs_pmg=round(t["pmg"] / max(t["pmg_learned_smoother"], 1e-9), 3),
+                       learned_smoother_iterations_vs_pmg=(res["pmg_learned_smoother"]["iterations"],
+                                                           res["pmg"]["iterations"]),
+                       best_learned_vs_pmg=round(t["pmg"] / max(min(t["learned"], t["learned_cheb4"],
+                                                                    t["pmg_learned_smoother"]), 1e-9), 3))
+    best_learned = min(t["learned"], t["learned_cheb4"], t["pmg_learned_smoother"])
     best_plain = min(t["jacobi"], t["chebyshev4"], t["chebyshev4_fp32"], t["pmg"])
     saved = best_plain - best_learned
     out["break_even_solves"] = (round((t_data + info["seconds"]) / saved, 1) if saved > 0 else None)
@@ -837,7 +849,7 @@ def main():
             return res
         out["vector"] = {f"p{pv}": run("vector", suite_vector_ir, pv, Nv) for pv, Nv in VECTOR_CASES}
         out["kappa_chebyshev"] = run("kappa", suite_kappa_cheb)
-        out["learned"] = run("learned", suite_learned)
+        out["learned"] = {f"p{pl}": run("learned", suite_learned, pl, Nl) for pl, Nl in LEARNED_CASES}
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)

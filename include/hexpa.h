@@ -491,10 +491,20 @@ typedef struct {
                           HX_BF16_SPLIT: as HX_FP32, with the finest level's
                           operator on the bf16 matrix cores (hx_op_apply_bf16;
                           scalar diffusion, p+1 <= 8, q <= 8)                   */
+  hx_mlp smoother_mlp; /* NULL: every smoother is Chebyshev on D_l^-1 A_l. A
+                          trained network (learned element preconditioner, see
+                          hx_op_mlp_precond): the finest level's smoother is
+                          the same Chebyshev polynomial with the mode-1 learned
+                          map M r = D^-1 r + correction in place of D^-1, on
+                          [lam_hi / smooth_ratio, lam_hi], lam_hi = 1.1 lam_max(M A)
+                          from lanczos_steps power iterations; prec HX_FP64 and
+                          scalar diffusion only (not in the paper: the learned
+                          map as a smoother inside the multigrid cycle)        */
 } hx_pmg_opts;
 
 /* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 30,
- * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations), HX_FP64. */
+ * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations), HX_FP64,
+ * no learned smoother. */
 void hx_pmg_opts_default(hx_pmg_opts *opts);
 
 /* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):
@@ -509,7 +519,8 @@ void hx_pmg_opts_default(hx_pmg_opts *opts);
  * HX_EBREAKDOWN (a lam_max estimate failed). */
 hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream s, hx_pmg *out);
 int hx_pmg_levels(hx_pmg mg);
-/* lam_max of D_l^-1 A_l as estimated at creation (0 for the coarsest level). */
+/* lam_max of D_l^-1 A_l as estimated at creation (0 for the coarsest level; of M A
+ * on level 0 with a learned smoother). */
 hx_status hx_pmg_lambda_max(hx_pmg mg, int level, double *lam_max);
 /* z = V_0 r (device FP64 L-vectors of level 0; z must not alias r). Synchronises s
  * at the coarse solve's convergence checks: once with coarse_rtol 0, otherwise at

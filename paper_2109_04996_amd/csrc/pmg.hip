@@ -18,6 +18,7 @@
 #include <numeric>
 
 #include "hx_internal.h"
+#include "mlp_internal.h"
 
 namespace hx {
 namespace {
@@ -274,6 +275,7 @@ extern "C" void hx_pmg_opts_default(hx_pmg_opts *o) {
   o->coarse_maxit = 30;
   o->coarse_rtol = 0.1;
   o->prec = HX_FP64;
+  o->smoother_mlp = nullptr;
 }
 
 extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream stream,
@@ -302,6 +304,14 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
     if (ops[l]->mesh->device != ops[0]->mesh->device) return fail(HX_EINVAL, "the levels are on different devices");
   }
   auto mg = std::make_unique<hx_pmg_s>();
+  if (o.smoother_mlp) {
+    if (o.prec != HX_FP64) return fail(HX_EUNSUPPORTED, "a learned smoother needs an FP64 hierarchy");
+    if (ops[0]->kind != HX_DIFFUSION || ops[0]->ncomp != 1)
+      return fail(HX_EUNSUPPORTED, "a learned smoother needs a scalar diffusion finest level");
+    const int P3 = ops[0]->P * ops[0]->P * ops[0]->P;
+    if (o.smoother_mlp->n_in != 2 * P3 || o.smoother_mlp->n_out != P3)
+      return fail(HX_EINVAL, "the smoother network's shape does not match the finest level");
+  }
   mg->opts = o;
   for (int l = 0; l < nlevels; ++l) {
     mg->lv.push_back(std::make_unique<hx_pmg_s::Level>());

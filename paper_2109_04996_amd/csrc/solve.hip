@@ -882,8 +882,29 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   auto &C = *mg.lv[l + 1];
   Vecs<T> vc;
   if (hx_status st = level_vecs(C, vc)) return st;
+  // a learned smoother on the finest level of an FP64 hierarchy: the same polynomial on the mode-1
+  // learned map M in place of D^-1 (v.cd, v.ct and v.m carry its recurrence; v.p and v.z the
+  // post-smoothing residual and correction)
+  const PrecFn<double> *learned = nullptr;
+  PrecFn<double> mlp_base;
+  if constexpr (std::is_same<T, double>::value) {
+    if (l == 0 && mg.opts.smoother_mlp) {
+      mlp_base = [&](const double *rr, double *zz) -> hx_status {
+        return mlp_precond_apply(*L.op, *mg.opts.smoother_mlp, 1, rr, zz, s);
+      };
+      learned = &mlp_base;
+    }
+  }
   // pre-smoothing from 0; the restriction reads the masked residual r - A z
-  if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
+  if constexpr (std::is_same<T, double>::value) {
+    if (learned) {
+      if (hx_status st = cheb_apply_base(c, ch, v, *learned, r, z)) return st;
+    } else {
+      if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
+    }
+  } else {
+    if (hx_status st = cheb_apply<T>(c, ch, v, r, z, op_prec)) return st;
+  }
   if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
   // coarse correction
   if (hx_status st = launch_restrict<T>(mg, (int)l, v.w, vc.r, C.op->mesh->freemask.ptr, s, r)) return st;
@@ -891,7 +912,18 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
   if (hx_status st = launch_prolong<T>(mg, (int)l, vc.x, v.w, fm, s)) return st;
   LAUNCH_V((k_add<T>), n, v.w, z);
   // post-smoothing: the same polynomial on the error equation, from the corrected iterate
-  if (hx_status st = cheb_apply_from<T>(c, ch, v, r, z, op_prec)) return st;
+  if constexpr (std::is_same<T, double>::value) {
+    if (learned) {
+      if (hx_status st = apply_T(c, z, v.w, op_prec)) return st;
+      LAUNCH_V((k_resid<double, double, 1>), n, 1.0, r, v.w, fm, v.p, c.part1);
+      if (hx_status st = cheb_apply_base(c, ch, v, *learned, v.p, v.z)) return st;
+      LAUNCH_V((k_add<T>), n, v.z, z);
+    } else {
+      if (hx_status st = cheb_apply_from<T>(c, ch, v, r, z, op_prec)) return st;
+    }
+  } else {
+    if (hx_status st = cheb_apply_from<T>(c, ch, v, r, z, op_prec)) return st;
+  }
   L.applies += c.applies;
   HX_HIP(hipGetLastError());
   return HX_OK;
@@ -941,8 +973,16 @@ hx_status pmg_setup_levels(hx_pmg_s &mg, hipStream_t s) {
       if (mg.opts.prec == HX_FP32 || l > 0)
         if (hx_status st = make_qdata32(op, s)) return st;
     }
-    if (l + 1 < mg.lv.size())
+    if (l == 0 && mg.opts.smoother_mlp) {
+      // the learned smoother's interval: lam_max of M A by power iteration
+      if (hx_status st = mlp_prepare(op, s)) return st;
+      PrecFn<double> base = [&](const double *rr, double *zz) -> hx_status {
+        return mlp_precond_apply(op, *mg.opts.smoother_mlp, 1, rr, zz, s);
+      };
+      if (hx_status st = power_lambda_max(c, v, base, mg.opts.lanczos_steps, &L.lam_max)) return st;
+    } else if (l + 1 < mg.lv.size()) {
       if (hx_status st = lanczos_lambda_max(c, v, mg.opts.lanczos_steps, &L.lam_max)) return st;
+    }
   }
   HX_HIP(hipStreamSynchronize(s));
   return HX_OK;

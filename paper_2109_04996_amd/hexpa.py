@@ -64,7 +64,8 @@ class hx_solve_opts(C.Structure):
 
 class hx_pmg_opts(C.Structure):
     _fields_ = [("smooth_degree", C.c_int), ("smooth_ratio", C.c_double), ("lanczos_steps", C.c_int),
-                ("coarse_maxit", C.c_int), ("coarse_rtol", C.c_double), ("prec", C.c_int)]
+                ("coarse_maxit", C.c_int), ("coarse_rtol", C.c_double), ("prec", C.c_int),
+                ("smoother_mlp", C.c_void_p)]
 
 
 class hx_train_opts(C.Structure):

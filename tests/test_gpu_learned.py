@@ -9,7 +9,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from oracle import fem  # noqa: E402
+from oracle import fem, solvers  # noqa: E402
 from oracle import mlp as omlp  # noqa: E402
 from paper_2109_04996_amd import hexpa as hx  # noqa: E402
 from paper_2109_04996_amd import learned  # noqa: E402
@@ -301,3 +301,102 @@ def test_learned_map_matches_oracle_composition(mode):
         assert np.linalg.norm(z - zo) <= 2e-2 * np.linalg.norm(zo)
     finally:
         hx.hx_mlp_destroy(net)
+
+
+def _learned_map(mesh, p, kp, A, prm, rounded):
+    """v -> M v, the mode-1 learned map composed on the CPU from the oracle (as in the test above): the
+    assembled diagonal, kappa at the oracle's node coordinates, the FP64 network forward of the library's
+    FP32 parameters (with the matrix cores' bf16 roundings of inputs, W1, hidden values and W2 when
+    ``rounded``), the 1/multiplicity weights and the D^-1/2 scalings, plus D^-1 v."""
+    P3 = (p + 1) ** 3
+    free = mesh["boundary"] == 0
+    d = fem.diagonal(A)
+    dis = np.where(free, 1.0 / np.sqrt(d), 0.0)
+    EN = mesh["elem_nodes"].astype(np.int64)
+    lk = np.log(fem.kappa_eval(kp, fem.node_coordinates(mesh, p)))[EN]
+    feat = np.where(free[EN], lk - lk.mean(axis=1, keepdims=True), 3.0)
+    W = _split(prm, 2 * P3, 128, P3)
+    w = np.where(free, 1.0 / np.bincount(EN.ravel(), minlength=mesh["nnodes"]), 0.0)
+
+    def M(v):
+        re = (dis * v)[EN]
+        nrm = np.linalg.norm(re, axis=1)
+        X = np.hstack([re / np.where(nrm > 0, nrm, 1.0)[:, None], feat])
+        if rounded:
+            Y = _bf16(np.tanh(_bf16(X) @ _bf16(W["W1"]).T + W["b1"])) @ _bf16(W["W2"]).T + W["b2"]
+        else:
+            Y, _ = omlp.forward(W, X)
+        out = np.zeros(mesh["nnodes"])
+        np.add.at(out, EN, nrm[:, None] * Y)
+        return dis * w * out + np.where(free, v / d, 0.0)
+    return M
+
+
+@pytest.mark.parametrize("weights", ["zero", "random"])
+def test_learned_smoother_vcycle_matches_oracle(weights):
+    # One V-cycle whose finest smoother is the Chebyshev polynomial on the learned map (mode 1) against
+    # the oracle's V-cycle with that map as the finest level's base (the library's lam_max per level, a
+    # coarse Jacobi-PCG of 8 iterations). Zero weights: the map is D^-1 exactly, so the general-base
+    # recurrence and the post-smoothing residual path must agree to 1e-10. Random weights: against the
+    # bf16-rounded composition; each of the six map applications agrees within 1e-3 in norm (the map
+    # test above), the V-cycle within 2e-2.
+    from oracle import pmg as opmg
+    from paper_2109_04996_amd.problem import Hierarchy
+    p, N, degrees = 3, 4, (3, 1)
+    P3 = (p + 1) ** 3
+    print(f"\n[case] learned smoother V-cycle weights={weights}", flush=True)
+    kp = kappa_field_params(1002, M=64)
+    ms = [rotate_elements(lattice_mesh(N, pl, warp="B", shuffle_seed=3), pl, 0.15, seed=4) for pl in degrees]
+    net = hx.hx_mlp_create(2 * P3, 128, P3, 5)
+    try:
+        prm = hx.hx_mlp_get_params(net)
+        # random weights of +-0.05: a correction about half the size of the Jacobi step
+        prm[:] = 0.0 if weights == "zero" else np.random.default_rng(9).uniform(-0.05, 0.05, prm.size)
+        hx.hx_mlp_set_params(net, prm)
+        with Hierarchy(N, degrees, rule="gauss", kappa=kp, meshes=ms, smooth_degree=3, smooth_ratio=15.0,
+                       coarse_maxit=8, coarse_rtol=0.0, smoother_mlp=net.value) as H:
+            levels = []
+            for l, (m, pl) in enumerate(zip(ms, degrees)):
+                A = fem.assemble(m, pl, pl + 2, "gauss", "diffusion", kappa=kp)
+                free = solvers.free_mask(m["boundary"])
+                P = opmg.prolongation(m, ms[l + 1], pl, degrees[l + 1]) if l + 1 < len(degrees) else None
+                base = _learned_map(m, pl, kp, A, prm, rounded=True) if l == 0 else None
+                levels.append(opmg.Level(A, free, H.lambda_max(l) if P is not None else 0.0, P, base=base))
+            assert H.lambda_max(0) > 0.0
+            r = np.random.default_rng(5).uniform(-1.0, 1.0, ms[0]["nnodes"]) * levels[0].f
+            zd = H.vcycle(H.fine.to_dev(r))
+            assert torch.equal(zd, H.vcycle(H.fine.to_dev(r)))  # the same bits twice
+            z = zd.cpu().numpy()
+            zr = opmg.vcycle(levels, r, degree=3, ratio=15.0, coarse_rtol=0.0, coarse_maxit=8)
+            assert np.all(z[~levels[0].free] == 0)
+            tol = 1e-10 if weights == "zero" else 2e-2
+            assert np.linalg.norm(z - zr) <= tol * np.linalg.norm(zr), np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    finally:
+        hx.hx_mlp_destroy(net)
+
+
+def test_learned_smoother_gain_record(trained):
+    # What the trained network adds as the finest smoother's base inside the p-multigrid cycle, on held-out
+    # coefficient seeds: flexible CG with that V-cycle against the same V-cycle with Jacobi-Chebyshev
+    # smoothing (the p-multigrid baseline) and against Jacobi-PCG (the learned forms' fallback). The record
+    # is printed; every form must reach 1e-8 in the FP64 true residual.
+    from paper_2109_04996_amd.problem import Hierarchy
+    net, _ = trained
+    p, N, degrees = 3, 6, (3, 1)
+    record = {}
+    for seed in (100, 101):
+        kp = kappa_field_params(seed, M=128)
+        with Hierarchy(N, degrees, rule="gauss", kappa=kp) as Hj, \
+                Hierarchy(N, degrees, rule="gauss", kappa=kp, smoother_mlp=net.value) as Hl:
+            b = Hj.fine.to_dev(np.random.default_rng(2).uniform(-1, 1, Hj.fine.n) * (Hj.fine.mesh["boundary"] == 0))
+            rec = {}
+            for name, fn in (("pmg_jacobi_smoother", lambda: Hj.solve(b, rtol=1e-8, check_every=1)),
+                             ("pmg_learned_smoother", lambda: Hl.solve(b, rtol=1e-8, check_every=1)),
+                             ("jacobi_pcg", lambda: Hj.fine.solve(b, rtol=1e-8, check_every=1))):
+                x, info = fn()
+                assert info["true_rel_residual"] <= 1.05e-8, (seed, name, info)
+                rec[name] = (info["iterations"], round(info["solve_seconds"], 5))
+            rec["lam_max_MA"] = round(Hl.lambda_max(0), 4)
+            rec["lam_max_DA"] = round(Hj.lambda_max(0), 4)
+            record[seed] = rec
+    print("\n[learned] p-multigrid smoother gain record (iterations, seconds):", record, flush=True)
