@@ -664,6 +664,9 @@ def main():
                                                        "commands)")
     ap.add_argument("--sweep", action="store_true",
                     help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
+    ap.add_argument("--pmc-workload", default="bp5", choices=["bp5", "general", "bp4"],
+                    help="workload of --pmc-run: BP5 p=7 48^3 (default), the same with 20%% of the elements rotated, "
+                         "or BP4 3-component p=7 q=9 32^3")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
     ap.add_argument("--cg-sweep", action="store_true",
@@ -716,6 +719,31 @@ def main():
     if a.cg_sweep:
         cg_sweep("BP5", 7, 8, "gll")
         cg_sweep("BP3", 7, 9, "gauss")
+        return
+    if a.pmc_run and a.pmc_workload != "bp5":
+        # reference copy of known size (1 GiB read + 1 GiB written), then 6 applies of the named workload
+        from paper_2109_04996_amd.inputs import rotate_elements
+        if a.pmc_workload == "general":
+            mesh_w = rotate_elements(lattice_mesh(48, 7, warp="A", shuffle_seed=0), 7, 0.2, seed=5)
+            pw = Problem(48, 7, 8, "gll", "diffusion", mesh=mesh_w)
+        else:
+            mesh_w = lattice_mesh(32, 7, warp="A", shuffle_seed=0)
+            pw = Problem(32, 7, 9, "gauss", "diffusion", ncomp=3, mesh=mesh_w)
+        xw = pw.to_dev(uniform_vector(mesh_w["nnodes"], 1, pw.ncomp))
+        yw = pw.zeros()
+        ref_a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
+        ref_b = torch.empty_like(ref_a)
+        ref_b.copy_(ref_a)
+        for _ in range(6):
+            pw.apply(xw, yw)
+        torch.cuda.synchronize()
+        ab = algorithmic_bytes(mesh_w["nnodes"], mesh_w["nelem"], 8, pw.q, 6, pw.ncomp)
+        st = pw.stats
+        launches = st["nstrip_colors"] if st["nstrips"] > 0 and pw.q == 8 else st["ncolors"]
+        print(json.dumps(dict(pmc_run=True, workload=a.pmc_workload, copy_bytes=2 << 30,
+                              algorithmic_bytes_per_apply=ab["total"], launches_per_apply=launches,
+                              index_mode=st["index_mode"])), flush=True)
+        pw.close()
         return
     N, p = a.N, a.p
     P = Q = p + 1
