@@ -186,6 +186,35 @@ def diagonal(A: sp.csr_matrix, ncomp: int = 1) -> np.ndarray:
     return np.repeat(d, ncomp) if ncomp > 1 else d
 
 
+def lor_mesh(mesh: dict, p: int) -> dict:
+    """The low-order refined mesh of a degree-p mesh (Preconditioning section: a low-order discretization
+    on a refined mesh, spectrally equivalent by the FEM-SEM equivalence): every element is split into p^3
+    trilinear sub-hexahedra whose corners are its GLL nodes, sub-hex (i, j, k) taking element-local nodes
+    (i + a, j + b, k + c), a, b, c in {0, 1}, as its vertex a + 2b + 4c. The nodes (and their coordinates,
+    the vertices here) are those of the degree-p mesh; assembling it with p = 1 and the 2-point Gauss rule
+    gives the low-order refined matrix."""
+    P = p + 1
+    E = mesh["nelem"]
+    en = mesh["elem_nodes"].reshape(E, P, P, P)  # [e][k][j][i]
+    subs = []
+    for k in range(p):
+        for j in range(p):
+            for i in range(p):
+                subs.append(np.stack([en[:, k + c, j + b, i + a] for c in (0, 1) for b in (0, 1) for a in (0, 1)],
+                                     axis=1))
+    ev = np.stack(subs, axis=1).reshape(E * p ** 3, 8)  # sub-hexes of element e are rows e p^3 .. (e+1) p^3 - 1
+    return dict(verts=node_coordinates(mesh, p), elem_verts=ev.astype(np.int64), elem_nodes=ev.astype(np.int32),
+                nnodes=mesh["nnodes"], nelem=E * p ** 3, boundary=mesh["boundary"])
+
+
+def assemble_lor(mesh: dict, p: int, kappa=None) -> sp.csr_matrix:
+    """The low-order refined diffusion matrix: Q1 on ``lor_mesh``, integrated with the 2-point GLL (vertex)
+    rule per direction, kappa at the vertices. The vertex rule makes each sub-hex matrix the tensor form
+    1D stiffness x lumped 1D mass that the FEM-SEM equivalence is stated for (the paper cites it without
+    fixing a rule; with the 2-point Gauss rule the equivalence constants grow with p)."""
+    return assemble(lor_mesh(mesh, p), 1, 2, "gll", "diffusion", kappa)
+
+
 def node_coordinates(mesh: dict, p: int) -> np.ndarray:
     """Physical coordinates of every L-node (the trilinear map at the element's GLL nodes)."""
     xn, _ = gll_rule(p)

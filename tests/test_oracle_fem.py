@@ -296,3 +296,54 @@ def test_helmholtz_forms(rule, p, q):
     assert abs(H - H.T).max() <= 1e-14 * abs(H).max()
     if mesh["nnodes"] <= 400:
         assert np.linalg.eigvalsh(H.toarray())[0] > 0.0
+
+
+def test_lor_degree_one_is_the_q1_operator():
+    # at p = 1 the refinement is trivial: the LOR matrix is the Q1 operator with the same vertex rule
+    from paper_2109_04996_amd.inputs import kappa_field_params
+    m = lattice_mesh(3, 1, warp="B", shuffle_seed=2)
+    kp = kappa_field_params(7, M=32)
+    L = fem.assemble_lor(m, 1, kp)
+    A = fem.assemble(m, 1, 2, "gll", "diffusion", kp)
+    assert abs(L - A).max() <= 1e-15 * abs(A).max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_lor_invariants_and_coordinate_function(p):
+    # constants in the kernel, symmetric; on mesh A (affine sub-hexes, constant detJ: the vertex rule is
+    # exact for grad x . grad x detJ) the coordinate functions give x'Lx = vol = 1 and x'Ly = 0; the
+    # sub-hexes fill the elements (their volumes add up to 1 on either mesh)
+    for warp in ("A", "B"):
+        m = lattice_mesh(3, p, warp=warp, shuffle_seed=1)
+        L = fem.assemble_lor(m, p)
+        assert abs(L - L.T).max() <= 1e-14 * abs(L).max()
+        assert np.abs(L @ np.ones(L.shape[0])).max() <= 1e-12 * abs(L).max()
+        lm = fem.lor_mesh(m, p)
+        assert lm["nelem"] == m["nelem"] * p ** 3
+        vol = fem.assemble(lm, 1, 3, "gauss", "mass").sum()
+        assert abs(vol - 1.0) <= 1e-13
+        if warp == "A":
+            X = fem.node_coordinates(m, p)
+            for d in range(3):
+                assert abs(X[:, d] @ L @ X[:, d] - 1.0) <= 1e-12
+            assert abs(X[:, 0] @ L @ X[:, 1]) <= 1e-12
+
+
+def test_lor_spectral_equivalence():
+    # FEM-SEM equivalence (Preconditioning section): the generalized eigenvalues of (A, L) on the free
+    # nodes stay in a band independent of p, for the GLL-collocated operator, while those of (A, D)
+    # spread with p. Mesh A, 2^3 (3^3 at p <= 3) elements.
+    import scipy.linalg as sl
+    kd = []
+    for p in (2, 3, 4, 6, 8):
+        N = 2 if p > 3 else 3
+        m = lattice_mesh(N, p, warp="A", shuffle_seed=1)
+        free = m["boundary"] == 0
+        A = fem.assemble(m, p, p + 1, "gll", "diffusion")[free][:, free].toarray()
+        L = fem.assemble_lor(m, p)[free][:, free].toarray()
+        ev = sl.eigh(A, L, eigvals_only=True)
+        assert 0.35 <= ev.min() and ev.max() <= 2.4, (p, ev.min(), ev.max())
+        d = np.diag(A)
+        evd = np.linalg.eigvalsh(A / np.sqrt(np.outer(d, d)))
+        kd.append(evd.max() / evd.min())
+    assert kd[-1] > 8 * kd[0], kd  # 23.6 at p = 2, 244 at p = 8

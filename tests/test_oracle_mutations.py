@@ -30,6 +30,8 @@ MUTANTS = {
     "kappa_axes_swapped": ("fem.py", "wd = er.w3 * det * kappa_eval(kappa, x)",
                            "wd = er.w3 * det * kappa_eval(kappa, x[:, ::-1])"),
     "lambda_max_unscaled": ("solvers.py", "S = sp.diags(s) @ Aii @ sp.diags(s)", "S = Aii"),
+    "lor_subhex_corner_order": ("fem.py", "for c in (0, 1) for b in (0, 1) for a in (0, 1)]",
+                                "for c in (0, 1) for a in (0, 1) for b in (0, 1)]"),
     "helmholtz_mass_scale": ("fem.py", "return (alpha * A + beta * B).tocsr()", "return (alpha * A + alpha * B).tocsr()"),
     "gll_weight_formula": ("quadrature.py", "w = 2.0 / (p * (p + 1) * Pp * Pp)", "w = 2.0 / (p * (p + 1) * Pp)"),
     "chebyshev_coefficient": ("solvers.py", "d = rho_new * rho * d + (2.0 * rho_new / delta) * M(res)",
@@ -45,7 +47,8 @@ MUTANTS = {
 PINS = {
     "fem.py": ("test_oracle_fem", ["test_mass_integrates_volume", "test_coordinate_function_forms",
                                    "test_diffusion_invariants", "test_collocated_diagonal_closed_form",
-                                   "test_kappa_location_closed_form", "test_helmholtz_forms"]),
+                                   "test_kappa_location_closed_form", "test_helmholtz_forms",
+                                   "test_lor_invariants_and_coordinate_function"]),
     "quadrature.py": ("test_oracle_quadrature", ["test_closed_forms", "test_exactness_degrees"]),
     "solvers.py": ("test_oracle_solvers", ["test_chebyshev_recurrence_equals_polynomial",
                                            "test_chebyshev_general_base_map", "test_lambda_max_lanczos_branch"]),
