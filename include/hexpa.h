@@ -61,7 +61,8 @@ enum {
 
 enum { HX_GAUSS = 0, HX_GLL = 1 };          /* quadrature rule families               */
 enum { HX_MASS = 0, HX_DIFFUSION = 1,       /* B and A of the bake-off problems       */
-       HX_HELMHOLTZ = 2 };                   /* alpha A + beta B (hx_op_create_helmholtz) */
+       HX_HELMHOLTZ = 2,                     /* alpha A + beta B (hx_op_create_helmholtz) */
+       HX_LOR = 3 };                         /* low-order refined diffusion (hx_op_create_lor) */
 /* Arithmetic precisions. HX_BF16: matrix-core products of operands rounded to
  * bfloat16, accumulated in FP32. HX_BF16_SPLIT: the same matrix cores with every
  * operand carried as hi + lo, both bfloat16 (lo the rounding error of hi), and the
@@ -205,6 +206,29 @@ hx_status hx_op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, const 
  * Errors: as hx_op_create; HX_EINVAL for alpha or beta out of range. */
 hx_status hx_op_create_helmholtz(hx_mesh mesh, hx_basis basis, int ncomp, double alpha, double beta,
                                  const hx_kappa_rff *kappa, hx_stream s, hx_op *out);
+
+/* Low-order refined (LOR) diffusion operator of a mesh (Preconditioning section: a
+ * spectrally equivalent sparse matrix from a low-order discretization on a refined
+ * mesh, by the FEM-SEM equivalence of tensor-product elements). Every element of
+ * degree p is split into p^3 trilinear sub-hexahedra whose corners are its GLL
+ * nodes; the matrix is the Q1 stiffness on them, integrated with the 2-point GLL
+ * (vertex) rule per direction, kappa (as for hx_op_create; NULL: 1) at the
+ * vertices, assembled on the device into ELL storage (width W <= 32 entries per
+ * row, 19 on a lattice). The operator has the mesh's nodes: hx_op_apply (FP64),
+ * hx_op_diagonal, hx_pcg_solve in HX_SOLVE_FP64 mode and the finest level of an
+ * FP64 p-multigrid hierarchy accept it; FP32, bf16, E-vector and learned-map
+ * entry points return HX_EUNSUPPORTED. A hierarchy whose finest level is this
+ * operator preconditions the high-order operator of the same mesh nodes
+ * (HX_PC_PMG). Synchronous. Device memory: W * nnodes * 12 bytes.
+ * Errors: HX_EINVAL, HX_EGEOM (a sub-hex corner with a non-positive Jacobian),
+ * HX_EUNSUPPORTED (p = 0 or a row longer than 32), HX_ENOMEM, HX_EHIP. */
+hx_status hx_op_create_lor(hx_mesh mesh, const hx_kappa_rff *kappa, hx_stream s, hx_op *out);
+
+/* The assembled LOR matrix, copied to the host in ELL layout: width receives W;
+ * cols [W][nnodes] int32 and vals [W][nnodes] FP64 (entry k of row t at k*nnodes
+ * + t; rows shorter than W repeat their own index with value 0). cols and vals
+ * may be NULL (width only). Errors: HX_EINVAL (null, not an LOR operator), HX_EHIP. */
+hx_status hx_op_lor_matrix(hx_op op, int *width, int32_t *cols, double *vals);
 
 /* y = A x on the whole L-vector (no boundary condition), FP64.
  * x, y: device, nnodes*ncomp doubles. y is overwritten. Asynchronous.
@@ -500,11 +524,15 @@ typedef struct {
                           from lanczos_steps power iterations; prec HX_FP64 and
                           scalar diffusion only (not in the paper: the learned
                           map as a smoother inside the multigrid cycle)        */
+  int cycles;          /* V-cycles per application (>= 1): z = V r, then
+                          z += V (r - A_0 z) cycles - 1 times (an approximate
+                          inverse of A_0 that tightens with cycles; > 1 in FP64
+                          hierarchies only)                                    */
 } hx_pmg_opts;
 
 /* Defaults: smooth_degree 3, smooth_ratio 15, 20 Lanczos steps, coarse_maxit 30,
  * coarse_rtol 0.1 (the coarse PCG checks its residual every 10 iterations), HX_FP64,
- * no learned smoother. */
+ * no learned smoother, one cycle. */
 void hx_pmg_opts_default(hx_pmg_opts *opts);
 
 /* Builds the hierarchy over ops[0..nlevels-1] (not owned; they must outlive it):

@@ -27,6 +27,11 @@ template <int P>
 hx_status launch_apply_P(const hx_op_s &op, Prec prec, bool eout, const ApplyArgs &a, hipStream_t s);
 
 hx_status launch_apply(const hx_op_s &op, Prec prec, bool out_elem, const ApplyArgs &a, hipStream_t s) {
+  if (op.kind == HX_LOR) {
+    if (prec != Prec::F64 || out_elem)
+      return fail(HX_EUNSUPPORTED, "the low-order refined operator applies in FP64 to L-vectors only");
+    return lor_apply(op, static_cast<const double *>(a.x), static_cast<double *>(a.y), s);
+  }
   switch (op.P) {
     case 2: return launch_apply_P<2>(op, prec, out_elem, a, s);
     case 3: return launch_apply_P<3>(op, prec, out_elem, a, s);
@@ -226,6 +231,7 @@ extern "C" hx_status hx_op_apply(hx_op op, const double *x, double *y, hx_stream
 extern "C" hx_status hx_op_apply_f32(hx_op op, int qdata_prec, const float *x, float *y, hx_stream s) {
   if (!op || !x || !y) return fail(HX_EINVAL, "null argument");
   if (qdata_prec != HX_FP64 && qdata_prec != HX_FP32) return fail(HX_EINVAL, "qdata_prec must be HX_FP64 or HX_FP32");
+  if (op->kind == HX_LOR) return fail(HX_EUNSUPPORTED, "the low-order refined operator applies in FP64 only");
   hipStream_t st = static_cast<hipStream_t>(s);
   if (qdata_prec == HX_FP32)
     if (hx_status e = make_qdata32(*op, st)) return e;

@@ -162,6 +162,10 @@ struct hx_op_s {
   hx::DevBuf<float> mlp_wmult;     // [n] 1 / multiplicity on free nodes, 0 on constrained ones
   hx::DevBuf<uint16_t> mlp_x16, mlp_h16;
   hx::DevBuf<float> mlp_y, mlp_rnorm;
+  // HX_LOR: the assembled low-order refined matrix, ELL [lor_w][nnodes] (column-major)
+  int lor_w = 0;
+  hx::DevBuf<int32_t> lor_col;
+  hx::DevBuf<double> lor_val;
   // bf16 matrix-core operator: FP32 tables and a bfloat16 copy of qdata (made on demand)
   hx::DevBuf<float> tab_bf16;
   hx::DevBuf<uint16_t> qdata_bf16;
@@ -222,6 +226,9 @@ hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s);
 hx_status launch_diagonal_tables(const hx_op_s &op, const double *interp, const double *grad, double *diag,
                                  hipStream_t s);
 hx_status launch_apply_bf16(hx_op_s &op, bool split, const float *x, float *y, hipStream_t s);
+// the low-order refined operator: y = L x (FP64 L-vectors) and its diagonal
+hx_status lor_apply(const hx_op_s &op, const double *x, double *y, hipStream_t s);
+hx_status lor_diagonal(const hx_op_s &op, double *diag, hipStream_t s);
 // the mesh's transpose restriction (gather_ptr, gather_slot), built on first call
 hx_status mesh_gather_csr(hx_mesh_s &m);
 // p-multigrid transfer between level l (fine) and l+1 on FP64 or FP32 vectors; fm: free mask applied to the

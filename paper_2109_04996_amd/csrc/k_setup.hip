@@ -224,6 +224,7 @@ hx_status launch_diagonal_tables(const hx_op_s &op, const double *interp, const 
 }
 
 hx_status launch_diagonal(hx_op_s &op, double *diag, hipStream_t s) {
+  if (op.kind == HX_LOR) return lor_diagonal(op, diag, s);
   DevBuf<double> dI, dG;
   HX_HIP(dI.upload(op.b.interp.data(), op.b.interp.size()));
   HX_HIP(dG.upload(op.b.grad.data(), op.b.grad.size()));

@@ -276,6 +276,7 @@ extern "C" void hx_pmg_opts_default(hx_pmg_opts *o) {
   o->coarse_rtol = 0.1;
   o->prec = HX_FP64;
   o->smoother_mlp = nullptr;
+  o->cycles = 1;
 }
 
 extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_opts *opts, hx_stream stream,
@@ -284,6 +285,8 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
   *out = nullptr;
   if (nlevels < 2 || nlevels > 8) return fail(HX_EINVAL, "nlevels must be in 2..8");
   const hx_pmg_opts &o = *opts;
+  if (o.cycles < 1 || (o.cycles > 1 && o.prec != HX_FP64))
+    return fail(HX_EINVAL, "cycles must be >= 1 (more than one cycle per application in FP64 hierarchies only)");
   if (o.smooth_degree < 1 || !(o.smooth_ratio > 1.0) || o.lanczos_steps < 2 || o.coarse_maxit < 1 ||
       !(o.coarse_rtol >= 0.0 && o.coarse_rtol < 1.0))
     return fail(HX_EINVAL, "need smooth_degree >= 1, smooth_ratio > 1, lanczos_steps >= 2, coarse_maxit >= 1, "
@@ -298,12 +301,16 @@ extern "C" hx_status hx_pmg_create(const hx_op *ops, int nlevels, const hx_pmg_o
     if (ops[l]->ncomp != ops[0]->ncomp) return fail(HX_EINVAL, "the levels' operators differ in components");
     if (ops[l]->mesh->nuntouched > 0) return fail(HX_EINVAL, "p-multigrid needs every node in some element");
     if (l == 0) continue;
-    if (ops[l]->kind != ops[0]->kind) return fail(HX_EINVAL, "the levels' operators differ in kind");
+    // a low-order refined finest level sits on diffusion levels of the same coefficient
+    const int kind0 = ops[0]->kind == HX_LOR ? HX_DIFFUSION : ops[0]->kind;
+    if (ops[l]->kind != kind0) return fail(HX_EINVAL, "the levels' operators differ in kind");
     if (ops[l]->P >= ops[l - 1]->P) return fail(HX_EINVAL, "degrees must decrease strictly from level 0");
     if (ops[l]->mesh->nelem != ops[0]->mesh->nelem) return fail(HX_EINVAL, "the levels' meshes differ in elements");
     if (ops[l]->mesh->device != ops[0]->mesh->device) return fail(HX_EINVAL, "the levels are on different devices");
   }
   auto mg = std::make_unique<hx_pmg_s>();
+  if (ops[0] && ops[0]->kind == HX_LOR && (o.prec != HX_FP64 || o.smoother_mlp))
+    return fail(HX_EUNSUPPORTED, "a low-order refined finest level needs an FP64 hierarchy without a learned smoother");
   if (o.smoother_mlp) {
     if (o.prec != HX_FP64) return fail(HX_EUNSUPPORTED, "a learned smoother needs an FP64 hierarchy");
     if (ops[0]->kind != HX_DIFFUSION || ops[0]->ncomp != 1)

@@ -932,7 +932,27 @@ hx_status pmg_level(hx_pmg_s &mg, size_t l, const T *r, T *z, hipStream_t s) {
 // z = V_0 r on FP64 vectors; an FP32 hierarchy converts at the finest level (its v.m and v.rp carry
 // the FP32 input and output: the level itself does not use them)
 hx_status pmg_vcycle(hx_pmg_s &mg, const double *r, double *z, hipStream_t s) {
-  if (mg.opts.prec == HX_FP64) return pmg_level<double>(mg, 0, r, z, s);
+  if (mg.opts.prec == HX_FP64) {
+    if (hx_status st = pmg_level<double>(mg, 0, r, z, s)) return st;
+    if (mg.opts.cycles > 1) {
+      // further cycles on the residual: z += V(r - A z), level 0's v.r and v.x (free at level 0) carry it
+      auto &L = *mg.lv[0];
+      Ctx c = level_ctx(mg, L, s);
+      Vecs<double> v;
+      if (hx_status st = level_vecs(L, v)) return st;
+      const uint8_t *fm = L.op->mesh->freemask.ptr;
+      for (int k = 1; k < mg.opts.cycles; ++k) {
+        if (hx_status st = apply_T(c, z, v.w, HX_FP64)) return st;
+        if (L.op->ncomp == 1) LAUNCH_V((k_resid<double, double, 1>), L.n, 1.0, r, v.w, fm, v.r, c.part1);
+        else LAUNCH_V((k_resid<double, double, 3>), L.n, 1.0, r, v.w, fm, v.r, c.part1);
+        if (hx_status st = pmg_level<double>(mg, 0, v.r, v.x, s)) return st;
+        LAUNCH_V((k_add<double>), L.n, v.x, z);
+      }
+      L.applies += c.applies;
+      HX_HIP(hipGetLastError());
+    }
+    return HX_OK;
+  }
   auto &L = *mg.lv[0];
   Ctx c = level_ctx(mg, L, s);
   Vecs<float> v;
@@ -1037,7 +1057,17 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   if (o.precond < HX_PC_NONE || o.precond > HX_PC_PMG) return fail(HX_EINVAL, "precond out of range");
   const bool pmg = o.precond == HX_PC_PMG;
   if (pmg && !o.pmg) return fail(HX_EINVAL, "HX_PC_PMG needs opts.pmg");
-  if (pmg && o.pmg->lv[0]->op != op) return fail(HX_EINVAL, "the hierarchy's finest operator is not the solved one");
+  // the hierarchy's finest operator is the solved one, or the low-order refined operator of its nodes
+  // (same node count, and the same coordinates at 1024 sampled nodes)
+  if (pmg && o.pmg->lv[0]->op != op) {
+    const hx_op_s &f = *o.pmg->lv[0]->op;
+    bool same = f.kind == HX_LOR && o.pmg->lv[0]->n == op->mesh->nnodes * op->ncomp &&
+                f.mesh->nnodes == op->mesh->nnodes;
+    const int64_t nn = op->mesh->nnodes;
+    for (int64_t t = 0; same && t < nn; t += std::max<int64_t>(1, nn / 1024))
+      for (int d = 0; d < 3; ++d) same = same && f.mesh->h_xyz[3 * t + d] == op->mesh->h_xyz[3 * t + d];
+    if (!same) return fail(HX_EINVAL, "the hierarchy's finest operator is not the solved one");
+  }
   if (pmg && o.mode != HX_SOLVE_FP64) return fail(HX_EUNSUPPORTED, "HX_PC_PMG runs in HX_SOLVE_FP64 mode");
   if (!(o.rtol > 0) || o.maxit < 1 || o.check_every < 1) return fail(HX_EINVAL, "need rtol > 0, maxit >= 1, check_every >= 1");
   const bool mlp = o.precond == HX_PC_MLP;
@@ -1069,6 +1099,9 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
     return fail(HX_EUNSUPPORTED, "the bf16 operator supports scalar diffusion only");
   if (o.scatter != HX_SCATTER_COLORS && o.scatter != HX_SCATTER_GATHER)
     return fail(HX_EINVAL, "scatter must be HX_SCATTER_COLORS or HX_SCATTER_GATHER");
+  if (op->kind == HX_LOR && (o.mode != HX_SOLVE_FP64 || (cheb && o.cheb_prec != HX_FP64) || mlp ||
+                             o.scatter != HX_SCATTER_COLORS))
+    return fail(HX_EUNSUPPORTED, "the low-order refined operator solves in FP64 with Jacobi, FP64 Chebyshev or p-multigrid");
   *info = hx_solve_info{};
   hipStream_t s = static_cast<hipStream_t>(stream);
   // graph replay needs a stream that can be captured: the solve then runs on the operator's own
@@ -1332,7 +1365,7 @@ extern "C" hx_status hx_pcg_solve(hx_op op, const double *b, double *x, const hx
   HX_HIP(hipStreamSynchronize(s));
   const auto t1 = std::chrono::steady_clock::now();
   info->solve_seconds = std::chrono::duration<double>(t1 - t0).count();
-  info->operator_applies = c.applies + (pmg ? (int)(o.pmg->lv[0]->applies - pmg_applies0) : 0);
+  info->operator_applies = c.applies + ((pmg && o.pmg->lv[0]->op == op) ? (int)(o.pmg->lv[0]->applies - pmg_applies0) : 0);
   double rr_true = 0;
   if (hx_status st = residual(&rr_true)) return st;
   info->true_rel_residual = std::sqrt(rr_true) / bn;
@@ -1423,9 +1456,13 @@ extern "C" hx_status hx_pcg_solve_noalloc(hx_op op, const double *b, double *x, 
     } else {
       // the diagonal into the seventh vector, its kernel reading the 1D tables staged in the scratch array
       double *d = vb + 6 * n, *ti = sc, *tg = sc + op->b.interp.size();
-      HX_HIP(hipMemcpyAsync(ti, op->b.interp.data(), sizeof(double) * op->b.interp.size(), hipMemcpyHostToDevice, s));
-      HX_HIP(hipMemcpyAsync(tg, op->b.grad.data(), sizeof(double) * op->b.grad.size(), hipMemcpyHostToDevice, s));
-      if (hx_status st = launch_diagonal_tables(*op, ti, tg, d, s)) return st;
+      if (op->kind == HX_LOR) {
+        if (hx_status st = lor_diagonal(*op, d, s)) return st;
+      } else {
+        HX_HIP(hipMemcpyAsync(ti, op->b.interp.data(), sizeof(double) * op->b.interp.size(), hipMemcpyHostToDevice, s));
+        HX_HIP(hipMemcpyAsync(tg, op->b.grad.data(), sizeof(double) * op->b.grad.size(), hipMemcpyHostToDevice, s));
+        if (hx_status st = launch_diagonal_tables(*op, ti, tg, d, s)) return st;
+      }
       dg = d;
     }
   }

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("HEXPA_LIB") or os.path.join(_PKG, "libhexpa.so")
 HX_OK, HX_EINVAL, HX_ERANGE, HX_EUNSUPPORTED, HX_EGEOM, HX_ENOCONV, HX_EBREAKDOWN, HX_EHIP, HX_ENOMEM = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 HX_GAUSS, HX_GLL = 0, 1
-HX_MASS, HX_DIFFUSION, HX_HELMHOLTZ = 0, 1, 2
+HX_MASS, HX_DIFFUSION, HX_HELMHOLTZ, HX_LOR = 0, 1, 2, 3
 HX_FP64, HX_FP32, HX_BF16, HX_BF16_SPLIT = 0, 1, 2, 3
 HX_PC_NONE, HX_PC_JACOBI, HX_PC_CHEBYSHEV, HX_PC_MLP, HX_PC_PMG = 0, 1, 2, 3, 4
 HX_SOLVE_FP64, HX_SOLVE_IR, HX_SOLVE_MIXED = 0, 1, 2
@@ -65,7 +65,7 @@ class hx_solve_opts(C.Structure):
 class hx_pmg_opts(C.Structure):
     _fields_ = [("smooth_degree", C.c_int), ("smooth_ratio", C.c_double), ("lanczos_steps", C.c_int),
                 ("coarse_maxit", C.c_int), ("coarse_rtol", C.c_double), ("prec", C.c_int),
-                ("smoother_mlp", C.c_void_p)]
+                ("smoother_mlp", C.c_void_p), ("cycles", C.c_int)]
 
 
 class hx_train_opts(C.Structure):
@@ -102,6 +102,8 @@ SIGNATURES = [
     ("hx_op_create", C.c_int, [_VP, _VP, C.c_int, C.c_int, C.POINTER(hx_kappa_rff), _VP, C.POINTER(_VP)]),
     ("hx_op_create_helmholtz", C.c_int, [_VP, _VP, C.c_int, C.c_double, C.c_double, C.POINTER(hx_kappa_rff), _VP,
                                          C.POINTER(_VP)]),
+    ("hx_op_create_lor", C.c_int, [_VP, C.POINTER(hx_kappa_rff), _VP, C.POINTER(_VP)]),
+    ("hx_op_lor_matrix", C.c_int, [_VP, C.POINTER(C.c_int), _VP, _VP]),
     ("hx_op_apply", C.c_int, [_VP, _VP, _VP, _VP]),
     ("hx_op_apply_f32", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("hx_op_apply_bf16", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
@@ -275,6 +277,26 @@ def hx_op_create_helmholtz(mesh, basis, ncomp, alpha, beta, kappa: dict | None =
            "hx_op_create_helmholtz")
     del keep
     return h
+
+
+def hx_op_create_lor(mesh, kappa: dict | None = None, stream=None):
+    h = C.c_void_p()
+    kp, keep = _kappa_struct(kappa)
+    _check(load().hx_op_create_lor(mesh, C.byref(kp) if kp is not None else None, _stream(stream), C.byref(h)),
+           "hx_op_create_lor")
+    del keep
+    return h
+
+
+def hx_op_lor_matrix(op, nnodes: int):
+    """(W, cols [W][nnodes] int32, vals [W][nnodes] float64) of a low-order refined operator."""
+    w = C.c_int()
+    _check(load().hx_op_lor_matrix(op, C.byref(w), None, None), "hx_op_lor_matrix")
+    cols = np.empty((w.value, nnodes), dtype=np.int32)
+    vals = np.empty((w.value, nnodes), dtype=np.float64)
+    _check(load().hx_op_lor_matrix(op, C.byref(w), cols.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p)),
+           "hx_op_lor_matrix")
+    return w.value, cols, vals
 
 
 def hx_op_apply(op, x, y, stream=None):

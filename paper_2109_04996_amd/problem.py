@@ -12,7 +12,7 @@ from . import hexpa as hx
 from . import inputs
 
 RULES = {"gauss": hx.HX_GAUSS, "gll": hx.HX_GLL}
-KINDS = {"mass": hx.HX_MASS, "diffusion": hx.HX_DIFFUSION, "helmholtz": hx.HX_HELMHOLTZ}
+KINDS = {"mass": hx.HX_MASS, "diffusion": hx.HX_DIFFUSION, "helmholtz": hx.HX_HELMHOLTZ, "lor": hx.HX_LOR}
 
 
 class Problem:
@@ -32,6 +32,9 @@ class Problem:
         self.h_basis = hx.hx_basis_create(p, q, RULES[rule])
         if kind == "helmholtz":
             self.h_op = hx.hx_op_create_helmholtz(self.h_mesh, self.h_basis, ncomp, helmholtz[0], helmholtz[1], kappa)
+        elif kind == "lor":
+            # the low-order refined matrix of the mesh (q and rule are not used)
+            self.h_op = hx.hx_op_create_lor(self.h_mesh, kappa)
         else:
             self.h_op = hx.hx_op_create(self.h_mesh, self.h_basis, KINDS[kind], ncomp, kappa)
         self.n = m["nnodes"] * ncomp
@@ -105,18 +108,22 @@ class Problem:
 class Hierarchy:
     """p-multigrid over polynomial degrees on one lattice mesh.
 
-    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, ncomp, helmholtz, **pmg_opts)``:
+    ``Hierarchy(N, degrees, rule, kind, warp, shuffle_seed, kappa, meshes, ncomp, helmholtz, lor, **pmg_opts)``:
     level l is a ``Problem`` of degree ``degrees[l]`` (strictly decreasing) with
     q = p + 1 GLL points or q = p + 2 Gauss points, on the same elements (same
-    shuffle); ``meshes`` overrides the lattice meshes level by level.
+    shuffle); ``meshes`` overrides the lattice meshes level by level. ``lor``: level 0
+    is the low-order refined operator of degree ``degrees[0]`` (a preconditioner for
+    the high-order operator of the same nodes), the others diffusion.
     """
 
     def __init__(self, N: int, degrees, rule: str = "gll", kind: str = "diffusion", warp="A", shuffle_seed=0,
-                 kappa: dict | None = None, meshes=None, ncomp: int = 1, helmholtz=(1.0, 1.0), **pmg_opts):
+                 kappa: dict | None = None, meshes=None, ncomp: int = 1, helmholtz=(1.0, 1.0), lor=False,
+                 **pmg_opts):
         self.levels = []
         for l, p in enumerate(degrees):
             q = p + 1 if rule == "gll" else p + 2
-            self.levels.append(Problem(N, p, q, rule, kind, ncomp=ncomp, warp=warp, shuffle_seed=shuffle_seed,
+            self.levels.append(Problem(N, p, q, rule, "lor" if (lor and l == 0) else kind, ncomp=ncomp, warp=warp,
+                                       shuffle_seed=shuffle_seed,
                                        kappa=kappa, mesh=None if meshes is None else meshes[l], helmholtz=helmholtz))
         self.h = hx.hx_pmg_create([pr.h_op for pr in self.levels], hx.hx_pmg_opts_default(**pmg_opts))
 

@@ -73,6 +73,10 @@ def test_null_handles(lib):
     assert lib.hx_op_diagonal(None, None, None) == hx.HX_EINVAL
     assert lib.hx_pcg_solve(None, None, None, None, None, None) == hx.HX_EINVAL
     assert lib.hx_pcg_solve_noalloc(None, None, None, None, None, None) == hx.HX_EINVAL
+    h = C.c_void_p()
+    assert lib.hx_op_create_lor(None, None, None, C.byref(h)) == hx.HX_EINVAL
+    assert lib.hx_op_create_lor(None, None, None, None) == hx.HX_EINVAL
+    assert lib.hx_op_lor_matrix(None, None, None, None) == hx.HX_EINVAL
     o = hx.hx_pmg_opts_default()
     h = C.c_void_p()
     assert lib.hx_pmg_create(None, 2, C.byref(o), None, C.byref(h)) == hx.HX_EINVAL
