@@ -10,6 +10,8 @@ namespace hx {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));  // 4 bf16 operands of a 16x16x16 MFMA
 typedef float f32x4 __attribute__((ext_vector_type(4)));   // its 4 FP32 accumulators
+typedef short bf16x8 __attribute__((ext_vector_type(8)));  // 8 bf16 operands (bit patterns) of a 16x16x32 MFMA
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));  // the same bits as that builtin's operand type
 
 // round to nearest even
 __host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {

@@ -120,6 +120,8 @@ struct hx_mesh_s {
   // transpose of the element restriction (made on first use): the E-vector slots e*P^3 + l (caller
   // element e, local node l) of each node, ascending; gather_ptr has nnodes + 1 entries
   hx::DevBuf<int32_t> gather_ptr, gather_slot;
+  // the same in internal element order: slots e * P^3 + l (internal position e), ascending (made on first use)
+  hx::DevBuf<int32_t> slot_ptr, slot_idx;
 };
 
 struct hx_op_s {
@@ -161,6 +163,9 @@ struct hx_op_s {
   hx::DevBuf<float> mlp_dis;       // [n] D^-1/2 on free nodes, 0 on constrained ones
   hx::DevBuf<float> mlp_wmult;     // [n] 1 / multiplicity on free nodes, 0 on constrained ones
   hx::DevBuf<uint16_t> mlp_x16, mlp_h16;
+  bool mlp_x16_feat = false;       // the coefficient half of the mlp_x16 rows is written
+  hx::DevBuf<float> mlp_dw;        // [n] D^-1/2 w (the output gather's node factor)
+  hx::DevBuf<double> mlp_dinv;     // [n] D^-1 on free nodes, 0 on constrained ones
   hx::DevBuf<float> mlp_y, mlp_rnorm;
   // HX_LOR: the assembled low-order refined matrix, ELL [lor_w][nnodes] (column-major)
   int lor_w = 0;
@@ -231,6 +236,8 @@ hx_status lor_apply(const hx_op_s &op, const double *x, double *y, hipStream_t s
 hx_status lor_diagonal(const hx_op_s &op, double *diag, hipStream_t s);
 // the mesh's transpose restriction (gather_ptr, gather_slot), built on first call
 hx_status mesh_gather_csr(hx_mesh_s &m);
+// the node -> element slot table in internal element order (slot_ptr, slot_idx), built on first call
+hx_status mesh_slots(hx_mesh_s &m);
 // p-multigrid transfer between level l (fine) and l+1 on FP64 or FP32 vectors; fm: free mask applied to the
 // output, or null
 template <typename T>

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_lor_kappa(int64_t n, const double *__re
 // cols [W][n] (padded with the node's own index). sptr/sslot: the element slots of each node
 // (internal element position e, local node l as e P^3 + l), ascending.
 __global__ void __launch_bounds__(kLorThreads)
-    k_lor_cols(int64_t n, int P, const int64_t *__restrict__ sptr, const int32_t *__restrict__ sslot,
+    k_lor_cols(int64_t n, int P, const int32_t *__restrict__ sptr, const int32_t *__restrict__ sslot,
                const int32_t *__restrict__ idx, int pass, int W, int32_t *__restrict__ cnt,
                int32_t *__restrict__ cols) {
   __shared__ int32_t nb[kLorThreads][kLorMaxW + 1];
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kLorThreads)
 // sub-hex matrix row of t, added at the columns of the sub-hex's corners. Rows are summed in
 // LDS (this thread's own), slots and sub-hexes in a fixed order.
 __global__ void __launch_bounds__(kLorThreads)
-    k_lor_vals(int64_t n, int P, const int64_t *__restrict__ sptr, const int32_t *__restrict__ sslot,
+    k_lor_vals(int64_t n, int P, const int32_t *__restrict__ sptr, const int32_t *__restrict__ sslot,
                const int32_t *__restrict__ idx, const double *__restrict__ xyz, const double *__restrict__ kn, int W,
                const int32_t *__restrict__ cols, double *__restrict__ vals, int *__restrict__ bad) {
   __shared__ int32_t sc[kLorThreads][kLorMaxW + 1];
@@ -212,24 +212,14 @@ unsigned lor_grid(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 25
 
 hx_status lor_assemble(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s) {
   hx_mesh_s &m = *op.mesh;
-  const int P = m.P, P3 = P * P * P;
-  const int64_t E = m.nelem, n = m.nnodes;
+  const int P = m.P;
+  const int64_t n = m.nnodes;
   if (P < 2) return fail(HX_EUNSUPPORTED, "the low-order refined operator needs p >= 1");
-  // node -> element slots, internal element order, ascending (a counting sort)
-  std::vector<int32_t> idx((size_t)E * P3);
-  HX_HIP(hipMemcpy(idx.data(), m.idx.ptr, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost));
-  std::vector<int64_t> ptr(n + 1, 0);
-  for (const int32_t nd : idx) ++ptr[nd + 1];
-  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
-  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
-  std::vector<int32_t> slot(idx.size());
-  for (int64_t e = 0; e < E; ++e)
-    for (int l = 0; l < P3; ++l) slot[fill[idx[(size_t)e * P3 + l]]++] = (int32_t)(e * P3 + l);
-  DevBuf<int64_t> dptr;
-  DevBuf<int32_t> dslot, dcnt;
+  // node -> element slots, internal element order, ascending (kept by the mesh)
+  if (hx_status st = mesh_slots(m)) return st;
+  const int32_t *sptr = m.slot_ptr.ptr, *sslot = m.slot_idx.ptr;
+  DevBuf<int32_t> dcnt;
   DevBuf<double> dk, dom, dph;
-  HX_HIP(dptr.upload(ptr.data(), ptr.size()));
-  HX_HIP(dslot.upload(slot.data(), slot.size()));
   HX_HIP(dcnt.alloc(n));
   HX_HIP(dk.alloc(n));
   KappaLor kap{0, nullptr, nullptr, 0.0, 0.0};
@@ -240,7 +230,7 @@ hx_status lor_assemble(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_lor_kappa, dim3(lor_grid(n)), dim3(256), 0, s, n, m.xyz.ptr, kap, dk.ptr);
   const unsigned nb = (unsigned)((n + kLorThreads - 1) / kLorThreads);
-  hipLaunchKernelGGL(k_lor_cols, dim3(nb), dim3(kLorThreads), 0, s, n, P, dptr.ptr, dslot.ptr, m.idx.ptr, 0, 0,
+  hipLaunchKernelGGL(k_lor_cols, dim3(nb), dim3(kLorThreads), 0, s, n, P, sptr, sslot, m.idx.ptr, 0, 0,
                      dcnt.ptr, (int32_t *)nullptr);
   HX_HIP(hipGetLastError());
   std::vector<int32_t> cnt(n);
@@ -251,12 +241,12 @@ hx_status lor_assemble(hx_op_s &op, const hx_kappa_rff *kappa, hipStream_t s) {
   op.lor_w = W;
   HX_HIP(op.lor_col.alloc((size_t)W * n));
   HX_HIP(op.lor_val.alloc((size_t)W * n));
-  hipLaunchKernelGGL(k_lor_cols, dim3(nb), dim3(kLorThreads), 0, s, n, P, dptr.ptr, dslot.ptr, m.idx.ptr, 1, W,
+  hipLaunchKernelGGL(k_lor_cols, dim3(nb), dim3(kLorThreads), 0, s, n, P, sptr, sslot, m.idx.ptr, 1, W,
                      dcnt.ptr, op.lor_col.ptr);
   DevBuf<int> dbad;
   HX_HIP(dbad.alloc(1));
   HX_HIP(hipMemsetAsync(dbad.ptr, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_lor_vals, dim3(nb), dim3(kLorThreads), 0, s, n, P, dptr.ptr, dslot.ptr, m.idx.ptr, m.xyz.ptr,
+  hipLaunchKernelGGL(k_lor_vals, dim3(nb), dim3(kLorThreads), 0, s, n, P, sptr, sslot, m.idx.ptr, m.xyz.ptr,
                      dk.ptr, W, op.lor_col.ptr, op.lor_val.ptr, dbad.ptr);
   HX_HIP(hipGetLastError());
   int bad = 0;

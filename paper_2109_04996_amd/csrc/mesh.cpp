@@ -557,6 +557,23 @@ hx_status mesh_gather_csr(hx_mesh_s &m) {
   return HX_OK;
 }
 
+hx_status mesh_slots(hx_mesh_s &m) {
+  if (m.slot_ptr.ptr) return HX_OK;
+  const int P3 = m.P * m.P * m.P;
+  const int64_t E = m.nelem, n = m.nnodes;
+  std::vector<int32_t> idx((size_t)E * P3);
+  HX_HIP(hipMemcpy(idx.data(), m.idx.ptr, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost));
+  std::vector<int32_t> ptr(n + 1, 0), slot(idx.size());
+  for (const int32_t nd : idx) ++ptr[nd + 1];
+  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t e = 0; e < E; ++e)
+    for (int l = 0; l < P3; ++l) slot[fill[idx[(size_t)e * P3 + l]]++] = (int32_t)(e * P3 + l);
+  HX_HIP(m.slot_ptr.upload(ptr.data(), ptr.size()));
+  HX_HIP(m.slot_idx.upload(slot.data(), slot.size()));
+  return HX_OK;
+}
+
 }  // namespace hx
 
 extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {

@@ -4,6 +4,7 @@
 // Not in the paper: the network is the element-local learned preconditioner added on top of
 // the method. Loss: mean squared error over every output entry of a batch. Adam: Kingma and
 // Ba (2015), with bias correction. Reductions (bias gradients, loss) are deterministic.
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -148,70 +149,139 @@ __global__ void k_f2bf(int64_t n, const float *__restrict__ a, uint16_t *__restr
     b[t] = f32_to_bf16_bits(a[t]);
 }
 
-// bf16 matrix-core forward of one layer: Out[M x N] = act(In[M x K] W^T + bias), W (N x K) bf16.
-// One wavefront owns 16 rows and NB = 128 output columns (8 MFMA tiles): each input row is read
-// once; the weights stay in L2. The input is FP32 (converted in registers) or bf16.
-template <typename TIN, bool TANH, typename TOUT>
-__global__ void __launch_bounds__(256)
-    k_layer_bf16(int64_t M, int N, int K, const TIN *__restrict__ In, const uint16_t *__restrict__ W,
-                 const float *__restrict__ bias, TOUT *__restrict__ Out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  const int n0 = blockIdx.y * 128;
-  if (m0 >= M) return;  // whole wavefront exits together
-  const int r = lane & 15, kb = 4 * (lane >> 4);
-  const int64_t row = m0 + r;
-  const bool rv = row < M;
-  f32x4 acc[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = k0 + kb + t;
-      float v = 0.f;
-      if (rv && k < K) v = to_float(In[row * K + k]);
-      a[t] = (short)f32_to_bf16_bits(v);
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int n = n0 + j * 16 + r;  // lane's column in this tile
-      bf16x4 b;
+// bf16 matrix-core forward of one layer: Out[M x N] = act(In[M x K] W^T + bias), W (N x K) bf16, both
+// row-major. gfx950's 16x16x32 bf16 product: lane l holds A[l%16][8(l/16) + t] and B[8(l/16) + t][l%16]
+// (t < 8) and receives D[4(l/16) + t][l%16] (t < 4) (layout checked on the device). One wavefront owns
+// 16 rows and NT tiles of 16 output columns, so a layer runs ceil(M/16) ceil(N/16 NT) wavefronts; per
+// 32-wide step of K a lane loads its 8 input values and, per tile, the 8 weights of its column, each as
+// one 16-byte load when K is a multiple of 8 (the rows are then 16-byte aligned). The input is FP32
+// (converted in registers) or bf16.
+template <typename TIN>
+__device__ __forceinline__ bf16x8 load8_bf16(const TIN *__restrict__ p, bool full, int valid) {
+  bf16x8 v;
+  if constexpr (std::is_same<TIN, uint16_t>::value) {
+    if (full) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(p);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int k = k0 + kb + t;
-        b[t] = (n < N && k < K) ? (short)W[(int64_t)n * K + k] : (short)0;
+        v[2 * t] = (short)(w[t] & 0xffffu);
+        v[2 * t + 1] = (short)(w[t] >> 16);
       }
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+      return v;
     }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = t < valid ? (short)p[t] : (short)0;
+  } else {
+    if (full) {
+      const float4 q0 = *reinterpret_cast<const float4 *>(p), q1 = *reinterpret_cast<const float4 *>(p + 4);
+      const float f[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = (short)f32_to_bf16_bits(f[t]);
+      return v;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = t < valid ? (short)f32_to_bf16_bits(p[t]) : (short)0;
   }
-  // accumulator: lane holds rows m0 + kb + t of column n0 + 16 j + r
+  return v;
+}
+
+template <typename TIN, bool TANH, typename TOUT, int NT, int RT, int U>
+__global__ void __launch_bounds__(256)
+    k_layer_bf16(int64_t M, int N, int K, const TIN *__restrict__ In, const uint16_t *__restrict__ W,
+                 const float *__restrict__ bias, const float *__restrict__ row_scale, TOUT *__restrict__ Out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // RT tiles of 16 rows share every weight load; consecutive blocks take the column groups of one row block
+  const int64_t m0 = ((int64_t)blockIdx.y * 4 + wave) * 16 * RT;
+  const int n0 = blockIdx.x * (16 * NT);
+  if (m0 >= M) return;  // whole wavefront exits together
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  const bool vec = (K & 7) == 0;
+  f32x4 acc[RT][NT];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int n = n0 + j * 16 + r;
-    if (n >= N) continue;
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t m = m0 + kb + t;
-      if (m >= M) continue;
-      float v = acc[j][t] + bias[n];
-      if (TANH) v = tanhf(v);
-      store_as(Out + m * N + n, v);
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  // U steps of 32 along K per iteration: every load of the U steps is issued before their products
+  for (int kb0 = 0; kb0 < K; kb0 += 32 * U) {
+    bf16x8 a[U][RT], b[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kb0 + 32 * u + kq, valid = K - k;  // this lane's 8 values along K: k .. k + 7
+      const bool full = vec && valid >= 8;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int64_t row = m0 + 16 * i + r;
+        a[u][i] = (row < M && valid > 0) ? load8_bf16<TIN>(In + row * K + k, full, valid) : zero8;
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int n = n0 + j * 16 + r;  // lane's column in this tile
+        b[u][j] = (n < N && valid > 0) ? load8_bf16<uint16_t>(W + (int64_t)n * K + k, full, valid) : zero8;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a[u][i]),
+                                                              __builtin_bit_cast(bf16x8_t, b[u][j]), acc[i][j], 0, 0, 0);
+  }
+  // accumulator: lane holds rows m0 + 16 i + 4 (lane / 16) + t of column n0 + 16 j + r
+  const int rb = 4 * (lane >> 4);
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int n = n0 + j * 16 + r;
+      if (n >= N) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = m0 + 16 * i + rb + t;
+        if (m >= M) continue;
+        float v = acc[i][j][t] + bias[n];
+        if (TANH) v = tanhf(v);
+        if (row_scale) v *= row_scale[m];
+        store_as(Out + m * N + n, v);
+      }
+    }
+}
+
+// launch one layer: NT = 2 column tiles and RT = 4 row tiles per wavefront up to 128 columns, else 4 and 2;
+// loads of U = 4 K steps in flight for K > 256, else 1; row_scale (optional) multiplies output row m
+template <typename TIN, bool TANH, typename TOUT>
+void launch_layer(int64_t M, int N, int K, const TIN *In, const uint16_t *W, const float *bias, TOUT *Out,
+                  hipStream_t s, const float *row_scale = nullptr) {
+  if (N <= 128) {
+    const dim3 g((unsigned)((N + 31) / 32), (unsigned)((M + 255) / 256));
+    if (K > 256)
+      hipLaunchKernelGGL((k_layer_bf16<TIN, TANH, TOUT, 2, 4, 4>), g, dim3(256), 0, s, M, N, K, In, W, bias, row_scale,
+                         Out);
+    else
+      hipLaunchKernelGGL((k_layer_bf16<TIN, TANH, TOUT, 2, 4, 1>), g, dim3(256), 0, s, M, N, K, In, W, bias, row_scale,
+                         Out);
+  } else {
+    const dim3 g((unsigned)((N + 63) / 64), (unsigned)((M + 127) / 128));
+    if (K > 256)
+      hipLaunchKernelGGL((k_layer_bf16<TIN, TANH, TOUT, 4, 2, 4>), g, dim3(256), 0, s, M, N, K, In, W, bias, row_scale,
+                         Out);
+    else
+      hipLaunchKernelGGL((k_layer_bf16<TIN, TANH, TOUT, 4, 2, 1>), g, dim3(256), 0, s, M, N, K, In, W, bias, row_scale,
+                         Out);
   }
 }
 
 }  // namespace
 
-hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uint16_t *H16, float *Y, hipStream_t s) {
+hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uint16_t *H16, float *Y, hipStream_t s,
+                          const float *row_scale) {
   if (hx_status st = mlp_refresh_bf16(net, s)) return st;
-  const dim3 g1((unsigned)((batch + 63) / 64), (unsigned)((net.n_hid + 127) / 128));
-  hipLaunchKernelGGL((k_layer_bf16<uint16_t, true, uint16_t>), g1, dim3(256), 0, s, batch, net.n_hid, net.n_in, X16,
-                     net.W1b.ptr, net.p.ptr + net.off_b1, H16);
-  const dim3 g2((unsigned)((batch + 63) / 64), (unsigned)((net.n_out + 127) / 128));
-  hipLaunchKernelGGL((k_layer_bf16<uint16_t, false, float>), g2, dim3(256), 0, s, batch, net.n_out, net.n_hid, H16,
-                     net.W2b.ptr, net.p.ptr + net.off_b2, Y);
+  launch_layer<uint16_t, true, uint16_t>(batch, net.n_hid, net.n_in, X16, net.W1b.ptr, net.p.ptr + net.off_b1, H16, s);
+  launch_layer<uint16_t, false, float>(batch, net.n_out, net.n_hid, H16, net.W2b.ptr, net.p.ptr + net.off_b2, Y, s,
+                                       row_scale);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
@@ -219,12 +289,10 @@ hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uin
 hx_status mlp_forward_bf16(hx_mlp_s &net, const float *X, int64_t batch, float *Y, hipStream_t s) {
   if (hx_status st = mlp_refresh_bf16(net, s)) return st;
   if (net.act16.count < (size_t)(batch * net.n_hid)) HX_HIP(net.act16.alloc((size_t)batch * net.n_hid));
-  const dim3 g1((unsigned)((batch + 63) / 64), (unsigned)((net.n_hid + 127) / 128));
-  hipLaunchKernelGGL((k_layer_bf16<float, true, uint16_t>), g1, dim3(256), 0, s, batch, net.n_hid, net.n_in, X,
-                     net.W1b.ptr, net.p.ptr + net.off_b1, net.act16.ptr);
-  const dim3 g2((unsigned)((batch + 63) / 64), (unsigned)((net.n_out + 127) / 128));
-  hipLaunchKernelGGL((k_layer_bf16<uint16_t, false, float>), g2, dim3(256), 0, s, batch, net.n_out, net.n_hid,
-                     net.act16.ptr, net.W2b.ptr, net.p.ptr + net.off_b2, Y);
+  launch_layer<float, true, uint16_t>(batch, net.n_hid, net.n_in, X, net.W1b.ptr, net.p.ptr + net.off_b1,
+                                     net.act16.ptr, s);
+  launch_layer<uint16_t, false, float>(batch, net.n_out, net.n_hid, net.act16.ptr, net.W2b.ptr, net.p.ptr + net.off_b2,
+                                       Y, s);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }

@@ -22,7 +22,9 @@ namespace hx {
 hx_status mlp_refresh_bf16(hx_mlp_s &net, hipStream_t s);
 hx_status mlp_forward_bf16(hx_mlp_s &net, const float *X, int64_t batch, float *Y, hipStream_t s);
 // both layers on bf16 inputs (rows of n_in), bf16 hidden activations H16 (rows of n_hidden), FP32 output
-hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uint16_t *H16, float *Y, hipStream_t s);
+// row_scale (optional, [batch]) multiplies each row of the output layer
+hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uint16_t *H16, float *Y, hipStream_t s,
+                          const float *row_scale = nullptr);
 // per-operator set-up of the learned preconditioner (node log kappa, element features and scales,
 // partition-of-unity weights); done once, on first use
 hx_status mlp_prepare(hx_op_s &op, hipStream_t s);

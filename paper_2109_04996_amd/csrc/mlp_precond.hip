@@ -7,15 +7,17 @@
 // log kappa at its nodes minus its mean, with the marker value kConstrained on constrained
 // nodes. The network's output, scaled back by |r~_e|, is an element correction c_e in the
 // scaled variables; the corrections are averaged at shared nodes (w = 1/multiplicity, a
-// partition of unity, 0 on constrained nodes), summed with the atomic-free colored scatter
-// G^T of the operator kernels, and mapped back: z = D^-1/2 G^T (w |r~_e| net(x_e)).
+// partition of unity, 0 on constrained nodes), summed over the elements of each node in a fixed
+// order (G^T as a node-wise gather, no atomics), and mapped back: z = D^-1/2 G^T (w |r~_e| net(x_e)).
 // In scaled variables the element block D_e^-1/2 A_ee D_e^-1/2 no longer depends on the size of
 // kappa or of the element, so one network serves all elements and mesh sizes; trained on
 // c_e = D_e^1/2 e_e - r~_e with e_e = A_ee^-1 r_e, z + D^-1 r is a restricted additive
 // Schwarz step over element blocks.
 //
-// Hot path: k_mlp_in (gather + scale + norm + bf16 features), two bf16 matrix-core layers over
-// all elements (mlp.hip), k_mlp_scatter per color.
+// Hot path: k_mlp_in (gather + scale + norm into bf16 rows), two bf16 matrix-core layers over all
+// elements (mlp.hip), k_mlp_gather_out (the node-wise sum over each node's element slots, with the
+// D^-1 r term of mode 1).
+#include <algorithm>
 #include <cmath>
 
 #include "mlp_internal.h"
@@ -98,55 +100,91 @@ __global__ void k_wmult(int64_t n, const uint8_t *__restrict__ fm, float *__rest
     w[t] = (fm[t] && w[t] > 0.f) ? 1.f / w[t] : 0.f;
 }
 
-// network input of each element: [r~_e / |r~_e|, feature] (bf16 rows, internal order) and |r~_e|
+// network input of each element: r~_e / |r~_e| into the first half of its bf16 row (internal order; the
+// second half, the element's coefficient feature, is written once per operator by k_mlp_feat) and
+// |r~_e|. One pass over the element's nodes: each thread keeps its (at most kMaxIn) values in
+// registers while the block sums the squares (wavefront shuffles, then one LDS slot per wavefront).
+// AFF: node ids from the element's affine numbering {base, s_j, s_k} (read with scalar loads) instead of
+// the full element restriction, so the gathers do not wait on an index load.
+constexpr int kMaxIn = (kMaxP * kMaxP * kMaxP + kThreads - 1) / kThreads;
+template <bool AFF>
 __global__ void __launch_bounds__(kThreads)
     k_mlp_in(int P, const int32_t *__restrict__ idx, const double *__restrict__ r, const float *__restrict__ dis,
-             const uint16_t *__restrict__ feat, uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
-  __shared__ double sh[kThreads];
+             uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
+  __shared__ double sh[kThreads / 64];
   const int64_t e = blockIdx.x;
-  const int P3 = P * P * P;
-  double s = 0.0;
-  for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const int64_t nd = idx[e * P3 + l];
-    const double v = (double)dis[nd] * r[nd];
-    s += v * v;
+  const int P2 = P * P, P3 = P2 * P;
+  int32_t base = 0, sj = 0, sk = 0;
+  if constexpr (AFF) {
+    base = idx[e * 4];
+    sj = idx[e * 4 + 1];
+    sk = idx[e * 4 + 2];
   }
-  const double nrm = sqrt(block_sum_d(s, sh));
+  double v[kMaxIn];
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kMaxIn; ++q) {
+    const int l = threadIdx.x + q * kThreads;
+    v[q] = 0.0;
+    if (l < P3) {
+      const int64_t nd = AFF ? (int64_t)base + l % P + (l / P) % P * sj + l / P2 * sk : idx[e * P3 + l];
+      v[q] = (double)dis[nd] * r[nd];
+      s += v[q] * v[q];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) tot += sh[w];
+  const double nrm = sqrt(tot);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   uint16_t *row = X16 + e * (int64_t)(2 * P3);
-  for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const int64_t nd = idx[e * P3 + l];
-    row[l] = f32_to_bf16_bits((float)((double)dis[nd] * r[nd] * inv));
-    row[P3 + l] = feat[e * P3 + l];
+#pragma unroll
+  for (int q = 0; q < kMaxIn; ++q) {
+    const int l = threadIdx.x + q * kThreads;
+    if (l < P3) row[l] = f32_to_bf16_bits((float)(v[q] * inv));
   }
   if (threadIdx.x == 0) rnorm[e] = (float)nrm;
 }
 
-// z[node] (+)= D^-1/2[node] w[node] |r~_e| y_e[l], colored: store by the first element, add by later ones
-__global__ void __launch_bounds__(kThreads)
-    k_mlp_scatter(int P, const int32_t *__restrict__ idx, const uint16_t *__restrict__ own,
-                  const float *__restrict__ Y, const float *__restrict__ rnorm, const float *__restrict__ dis,
-                  const float *__restrict__ w, double *__restrict__ z, int64_t e_begin) {
-  const int64_t e = e_begin + blockIdx.x;
-  const int P2 = P * P, P3 = P2 * P;
-  const double sc = (double)rnorm[e];
-  for (int l = threadIdx.x; l < P3; l += kThreads) {
-    const int k = l / P2;
-    const int64_t nd = idx[e * P3 + l];
-    const double v = (double)dis[nd] * (double)w[nd] * sc * (double)Y[e * (int64_t)P3 + l];
-    if ((own[e * P2 + (l % P2)] >> k) & 1u)
-      z[nd] = v;
-    else
-      z[nd] += v;
+// the coefficient half of every element's network input row (constant for an operator)
+__global__ void k_mlp_feat(int64_t E, int P3, const uint16_t *__restrict__ feat, uint16_t *__restrict__ X16) {
+  const int64_t total = E * P3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / P3, l = t - e * P3;
+    X16[e * 2 * P3 + P3 + l] = feat[t];
   }
 }
 
-// z += D^-1 r on free nodes (the Jacobi step of the mode-1 map)
-__global__ void k_jacobi_add(int64_t n, const double *__restrict__ diag, const uint8_t *__restrict__ fm,
-                             const double *__restrict__ r, double *__restrict__ z) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    if (fm[t]) z[t] += (1.0 / diag[t]) * r[t];
+// z[t] = (D^-1/2 w)[t] sum over the element slots of t (ascending) of |r~_e| y_e[l] (Ys holds the output rows
+// already scaled by |r~_e|), plus D^-1 r in mode 1 (dinv 0 on constrained nodes): one thread per node, the
+// corrections summed in a fixed order (no colors, no atomics).
+__global__ void __launch_bounds__(256)
+    k_mlp_gather_out(int64_t n, const int32_t *__restrict__ sptr, const int32_t *__restrict__ sslot,
+                     const float *__restrict__ Ys, const float *__restrict__ dw, int mode, const double *__restrict__ dinv,
+                     const double *__restrict__ r, double *__restrict__ z) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int32_t k = sptr[t]; k < sptr[t + 1]; ++k) s += (double)Ys[sslot[k]];
+    double v = (double)dw[t] * s;
+    if (mode == 1) v += dinv[t] * r[t];
+    z[t] = v;
+  }
 }
+
+// (D^-1/2 w)[t] and D^-1[t] on free nodes (1 / diag), 0 on constrained ones
+__global__ void k_mlp_factors(int64_t n, const float *__restrict__ dis, const float *__restrict__ w,
+                              const double *__restrict__ diag, const uint8_t *__restrict__ fm, float *__restrict__ dw,
+                              double *__restrict__ dinv) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    dw[t] = (float)((double)dis[t] * (double)w[t]);
+    dinv[t] = fm[t] ? 1.0 / diag[t] : 0.0;
+  }
+}
+
 
 // training features in caller element order (FP32): [r~_e / |r~_e|, feature]; |r~_e|
 __global__ void __launch_bounds__(kThreads)
@@ -227,6 +265,11 @@ hx_status mlp_prepare(hx_op_s &op, hipStream_t s) {
                          op.mlp_wmult.ptr, e0);
   }
   hipLaunchKernelGGL(k_wmult, dim3(2048), dim3(256), 0, s, n, m.freemask.ptr, op.mlp_wmult.ptr);
+  if (hx_status st = mesh_slots(*op.mesh)) return st;  // the node -> element slot table of the output gather
+  HX_HIP(op.mlp_dw.alloc(n));
+  HX_HIP(op.mlp_dinv.alloc(n));
+  hipLaunchKernelGGL(k_mlp_factors, dim3(2048), dim3(256), 0, s, n, op.mlp_dis.ptr, op.mlp_wmult.ptr, op.diag.ptr,
+                     m.freemask.ptr, op.mlp_dw.ptr, op.mlp_dinv.ptr);
   HX_HIP(hipGetLastError());
   HX_HIP(hipStreamSynchronize(s));  // om/ph are freed on return
   op.mlp_ready = true;
@@ -243,22 +286,27 @@ hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, int mode, const double *
   const int64_t E = m.nelem;
   if (op.mlp_x16.count < (size_t)(E * 2 * P3)) {
     HX_HIP(op.mlp_x16.alloc((size_t)E * 2 * P3));
+    op.mlp_x16_feat = false;
     HX_HIP(op.mlp_h16.alloc((size_t)E * net.n_hid));
     HX_HIP(op.mlp_y.alloc((size_t)E * P3));
   }
   if (op.mlp_h16.count < (size_t)(E * net.n_hid)) HX_HIP(op.mlp_h16.alloc((size_t)E * net.n_hid));
-  hipLaunchKernelGGL(k_mlp_in, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, r, op.mlp_dis.ptr,
-                     op.mlp_feat16.ptr, op.mlp_x16.ptr, op.mlp_rnorm.ptr);
-  if (hx_status st = mlp_layers_bf16(net, op.mlp_x16.ptr, E, op.mlp_h16.ptr, op.mlp_y.ptr, s)) return st;
-  if (m.nuntouched > 0) HX_HIP(hipMemsetAsync(z, 0, sizeof(double) * m.nnodes, s));
-  for (int c = 0; c < m.ncolors; ++c) {
-    const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
-    if (e1 > e0)
-      hipLaunchKernelGGL(k_mlp_scatter, dim3((unsigned)(e1 - e0)), dim3(kThreads), 0, s, op.P, m.idx.ptr, m.own.ptr,
-                         op.mlp_y.ptr, op.mlp_rnorm.ptr, op.mlp_dis.ptr, op.mlp_wmult.ptr, z, e0);
+  if (!op.mlp_x16_feat) {
+    hipLaunchKernelGGL(k_mlp_feat, dim3(2048), dim3(256), 0, s, E, P3, op.mlp_feat16.ptr, op.mlp_x16.ptr);
+    op.mlp_x16_feat = true;
   }
-  if (mode == 1)
-    hipLaunchKernelGGL(k_jacobi_add, dim3(2048), dim3(256), 0, s, m.nnodes, op.diag.ptr, m.freemask.ptr, r, z);
+  if (m.idx_affine.ptr)
+    hipLaunchKernelGGL(k_mlp_in<true>, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx_affine.ptr, r,
+                       op.mlp_dis.ptr, op.mlp_x16.ptr, op.mlp_rnorm.ptr);
+  else
+    hipLaunchKernelGGL(k_mlp_in<false>, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, r, op.mlp_dis.ptr,
+                       op.mlp_x16.ptr, op.mlp_rnorm.ptr);
+  // the output rows come out scaled by |r~_e|
+  if (hx_status st = mlp_layers_bf16(net, op.mlp_x16.ptr, E, op.mlp_h16.ptr, op.mlp_y.ptr, s, op.mlp_rnorm.ptr))
+    return st;
+  const int64_t n = m.nnodes;
+  hipLaunchKernelGGL(k_mlp_gather_out, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, n,
+                     m.slot_ptr.ptr, m.slot_idx.ptr, op.mlp_y.ptr, op.mlp_dw.ptr, mode, op.mlp_dinv.ptr, r, z);
   HX_HIP(hipGetLastError());
   return HX_OK;
 }
