@@ -350,6 +350,67 @@ def suite_kappa_cheb(p=6, N=61, kappa_seed=100):
     return _speedups(out)
 
 
+LOR_CASES = ((3, 57), (5, 35), (7, 25))  # (p, N): 5.1M to 5.5M DOFs
+
+
+def suite_lor(p=5, N=35, kappa_seed=100):
+    """Low-order refined preconditioning (Preconditioning section, FEM-SEM equivalence): the assembled LOR
+    matrix (setup time, ELL SpMV rate against its bytes), and flexible CG on the high-order operator with
+    the V-cycle of the hierarchy whose finest level is the LOR matrix, against Jacobi-PCG and the
+    high-order p-multigrid V-cycle. Variable coefficient (seed 100), GLL-collocated q = p + 1, b = B 1."""
+    import torch
+
+    from paper_2109_04996_amd import hexpa as hx
+    from paper_2109_04996_amd import learned
+    from paper_2109_04996_amd.inputs import kappa_field_params, lattice_mesh
+    from paper_2109_04996_amd.problem import Problem
+    print(f"[bench] LOR suite p={p} N={N}", file=sys.stderr, flush=True)
+    kp = kappa_field_params(kappa_seed, M=512)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    pr = Problem(N, p, p + 1, "gll", "diffusion", mesh=mesh, kappa=kp)
+    mass = Problem(N, p, p + 2, "gauss", "mass", mesh=mesh)
+    b = learned.rhs_ones(pr, mass)
+    mass.close()
+    n = mesh["nnodes"]
+    ref = reference_solution(pr, b, "gll", kappa=kp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lor = Problem(N, p, p + 1, "gll", "lor", mesh=mesh, kappa=kp)
+    torch.cuda.synchronize()
+    t_lor = time.perf_counter() - t0
+    w = lor_width(lor)
+    spmv_bytes = (12 * w + 16) * n  # ELL column and value per entry, x read once, y written once
+    out = dict(workload=f"diffusion with kappa (seed {kappa_seed}), p={p}, q={p + 1} GLL-collocated, mesh A {N}^3, "
+                        f"{n} DOFs, b = B 1, rtol 1e-8; reference: FP64 solve to 1e-12",
+               lor_assembly_seconds=round(t_lor, 3), lor_width=w,
+               lor_spmv=dict(bound="hbm", peak=HBM_PEAK_GBS, **apply_line(lor, spmv_bytes, n)))
+    _, out["fp64_jacobi"] = _timed_solve(pr, b, ref)
+    t0 = time.perf_counter()
+    coarse = [Problem(N, pc, pc + 1, "gll", "diffusion", mesh=lattice_mesh(N, pc, warp="A", shuffle_seed=0), kappa=kp)
+              for pc in pmg_degrees(p)[1:]]
+    mg = hx.hx_pmg_create([lor.h_op] + [c.h_op for c in coarse], hx.hx_pmg_opts_default())
+    mg_setup = time.perf_counter() - t0
+    _, out["fp64_fcg_lor_vcycle"] = _timed_solve(pr, b, ref, precond=hx.HX_PC_PMG, pmg=mg.value)
+    out["fp64_fcg_lor_vcycle"].update(degrees=pmg_degrees(p), hierarchy_setup_seconds=round(mg_setup + t_lor, 3))
+    hx.hx_pmg_destroy(mg)
+    for c in coarse:
+        c.close()
+    lor.close()
+    _pmg_form(pr, b, ref, "gll", out, "fp64_fcg_pmg", kappa=kp)
+    pr.close()
+    return _speedups(out)
+
+
+def lor_width(pr):
+    """ELL width of a low-order refined operator."""
+    import ctypes
+
+    from paper_2109_04996_amd import hexpa as hx
+    w = ctypes.c_int()
+    hx._check(hx.load().hx_op_lor_matrix(pr.h_op, ctypes.byref(w), None, None), "hx_op_lor_matrix")
+    return w.value
+
+
 LEARNED_CASES = ((4, 43), (5, 35), (6, 29), (7, 25))  # (p, N_eval): 5.2M to 5.5M DOFs
 
 
@@ -877,6 +938,7 @@ def main():
             return res
         out["vector"] = {f"p{pv}": run("vector", suite_vector_ir, pv, Nv) for pv, Nv in VECTOR_CASES}
         out["kappa_chebyshev"] = run("kappa", suite_kappa_cheb)
+        out["lor"] = {f"p{pl}": run("lor", suite_lor, pl, Nl) for pl, Nl in LOR_CASES}
         out["learned"] = {f"p{pl}": run("learned", suite_learned, pl, Nl) for pl, Nl in LEARNED_CASES}
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
