@@ -141,21 +141,36 @@ __device__ __forceinline__ void elem_sync() {
 // write another wait for every read before writing
 // HELM (diffusion only): the Helmholtz operator alpha A + beta B; qm [e][qc][qb][qa] = beta * w * detJ, and
 // the mass term qm * u joins the r3 line's sum before the transposed interpolations.
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false, bool HELM = false>
+// QLDS: the caller has the element's pointwise data (qd's layout for one element) on its way to LDS at qs;
+// stage() writes it there and is called once, right after the first pass's LDS writes, so that the
+// loads overlap the node gather and the first interpolation; the pointwise step then reads qs, and
+// the old values of the scatter are requested two passes earlier.
+struct NoStage {
+  __device__ void operator()() const {}
+};
+// LS, PL: LDS strides (doubles) of the r2 rows and r3 planes of a buffer, AT(i, j, k) = k PL + j LS + i.
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false, bool HELM = false,
+          bool QLDS = false, typename Stage = NoStage, int LS = Q + 1, int PL = Q *(Q + 1)>
 __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool lane_live,
                                               int64_t e, int c, const TQ *__restrict__ qd, const T *__restrict__ tab,
                                               const T *__restrict__ x, const int32_t (&nid)[P], uint32_t ob,
                                               const T *__restrict__ zero, const T *__restrict__ y, T (&old)[P],
-                                              T (&z)[P], const TQ *__restrict__ qm = nullptr) {
+                                              T (&z)[P], const TQ *__restrict__ qm = nullptr,
+                                              const TQ *qs = nullptr, Stage stage = Stage()) {
   static_assert(!HELM || MODE == MODE_DIFF, "the Helmholtz mass term rides on the diffusion pipeline");
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
-  constexpr int LS = Q + 1, PL = Q * LS;
+  static_assert(LS >= Q && PL >= (Q - 1) * LS + Q, "lines, rows and planes do not overlap");
 #define AT(i, j, k) ((k) * PL + (j) * LS + (i))
   const T *const tI = tab + Q * P + Q * Q;       // even-odd interpolation
   const T *const tD = tI + EOInterp<P, Q>::size;  // even-odd derivative
   // node lanes: (i, j) = (a, b) for a, b < P; the others address node (min(a, P-1), min(b, P-1))
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
+  // old values of the nodes this lane read-modify-writes (no other element of this launch touches them)
+  auto load_old = [&]() {
+#pragma unroll
+    for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
+  };
     // ---- interpolate along r3 in registers: thread (i, j), S0[i][j][qk]
     {
       T u[P], uq[Q];
@@ -166,6 +181,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 #pragma unroll
         for (int q = 0; q < Q; ++q) S0[AT(a, b, q)] = uq[q];
       }
+      if constexpr (QLDS) stage();
     }
     elem_sync<NT>();
     // ---- along r2: thread (i = a < P, qk = b), S1[i][qj][qk]
@@ -192,10 +208,17 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
     T w[Q];  // the field after the pointwise step and the transposed derivatives, on r3 lines of (a, b)
     if constexpr (MODE == MODE_MASS) {
       // pointwise on the r1 line: qdata (qi, qj=a, qk=b) is contiguous in qi
-      const TQ *const ql = qd + e * Q3 + b * Q2 + a * Q;
       T v[Q];
+      if constexpr (QLDS) {
+        const TQ *const ql = qs + b * Q2 + a * Q;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) v[q] = ul[q] * ld_q<NC, TQ, T>(ql + q);
+        for (int q = 0; q < Q; ++q) v[q] = ul[q] * static_cast<T>(ql[q]);
+        load_old();
+      } else {
+        const TQ *const ql = qd + e * Q3 + b * Q2 + a * Q;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = ul[q] * ld_q<NC, TQ, T>(ql + q);
+      }
       // transposed interpolation along r1 straight from registers: S0[i][qj][qk]
       T z[P];
       interp_bwd<P, Q, T>(tI, v, z);
@@ -246,30 +269,49 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
           for (int q = 0; q < Q; ++q) S0[AT(a, q, b)] = us[q];
         }
       }
-      // plane-ahead pointwise data (planes along r3 of the (qi = a, qj = b) column)
-      const TQ *const qe = qd + e * (6 * Q3) + b * Q + a;
-      T ga[6], gb[6];
-      auto load_plane = [&](T(&g)[6], int k) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m) g[m] = ld_q<NC, TQ, T>(qe + (k * 6 + m) * Q2);
-      };
-      load_plane(ga, 0);
-      load_plane(gb, 1);
-      elem_sync<NT>();
       // pointwise on r3 lines: thread (qi = a, qj = b); S1 holds ur, S0 us; vr -> S1, vs -> S0
       T vt[Q];
+      if constexpr (QLDS) {
+        // the element's pointwise data is in LDS (planes along r3 of the (qi = a, qj = b) column)
+        const TQ *const qp = qs + b * Q + a;
+        elem_sync<NT>();
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        T(&g)[6] = (k & 1) ? gb : ga;
-        const T r = S1[AT(a, b, k)], s = S0[AT(a, b, k)];
-        const T t = ut[k];
-        if (lane_live) {
-          S1[AT(a, b, k)] = g[0] * r + g[1] * s + g[2] * t;
-          S0[AT(a, b, k)] = g[1] * r + g[3] * s + g[4] * t;
+        for (int k = 0; k < Q; ++k) {
+          T g[6];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) g[m] = static_cast<T>(qp[(k * 6 + m) * Q2]);
+          const T r = S1[AT(a, b, k)], s = S0[AT(a, b, k)];
+          const T t = ut[k];
+          if (lane_live) {
+            S1[AT(a, b, k)] = g[0] * r + g[1] * s + g[2] * t;
+            S0[AT(a, b, k)] = g[1] * r + g[3] * s + g[4] * t;
+          }
+          vt[k] = g[2] * r + g[4] * s + g[5] * t;
         }
-        vt[k] = g[2] * r + g[4] * s + g[5] * t;
-        if (k + 2 < Q) load_plane(g, k + 2);
-        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        // plane-ahead pointwise data (planes along r3 of the (qi = a, qj = b) column)
+        const TQ *const qe = qd + e * (6 * Q3) + b * Q + a;
+        T ga[6], gb[6];
+        auto load_plane = [&](T(&g)[6], int k) {
+#pragma unroll
+          for (int m = 0; m < 6; ++m) g[m] = ld_q<NC, TQ, T>(qe + (k * 6 + m) * Q2);
+        };
+        load_plane(ga, 0);
+        load_plane(gb, 1);
+        elem_sync<NT>();
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          T(&g)[6] = (k & 1) ? gb : ga;
+          const T r = S1[AT(a, b, k)], s = S0[AT(a, b, k)];
+          const T t = ut[k];
+          if (lane_live) {
+            S1[AT(a, b, k)] = g[0] * r + g[1] * s + g[2] * t;
+            S0[AT(a, b, k)] = g[1] * r + g[3] * s + g[4] * t;
+          }
+          vt[k] = g[2] * r + g[4] * s + g[5] * t;
+          if (k + 2 < Q) load_plane(g, k + 2);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
       deriv_bwd<Q, T>(tD, vt, w);  // r3 part, on the r3 line of (a, b)
       if constexpr (HELM) {
@@ -311,6 +353,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 #pragma unroll
         for (int k = 0; k < Q; ++k) S0[AT(a, b, k)] = w[k];
       }
+      if constexpr (QLDS) load_old();
       elem_sync<NT>();
       // transposed interpolation along r1: thread (qj = a, qk = b), S0[i][qj][qk]
       {
@@ -338,10 +381,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
         for (int j = 0; j < P; ++j) S1[AT(a, j, b)] = z[j];
       }
     }
-    // old values of the nodes this lane read-modify-writes (no other element of this launch
-    // touches them), requested before the last contraction
-#pragma unroll
-    for (int k = 0; k < P; ++k) old[k] = *((ob & (1u << k)) ? zero : y + (int64_t)nid[k] * NC + c);
+    if constexpr (!QLDS) load_old();  // requested before the last contraction
     elem_sync<NT>();
     // ---- transposed interpolation along r3 in registers: thread (i, j) -> node line (i, j, 0..P-1)
     {
@@ -389,6 +429,93 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   T old[P], z[P];
   gauss_element<P, Q, MODE, NC, T, TQ, NT, false, HELM>(S0, S1, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y,
                                                        old, z, qm);
+  if (node_lane) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
+  }
+}
+
+// Threads of the joint-component kernel: the NC Q x Q line tiles of an element, packed end to end
+// and rounded up to whole wavefronts (Q = 9, NC = 3: 243 of 256 lanes live, against 81 of 128 with
+// one workgroup per component; Q = 8: 192 of 192).
+// LDS layout of its per-component buffers (strides in doubles): LS between r2 rows, PL between r3
+// planes, CS between the components' buffers. Chosen, with the component-minor lane order, by
+// counting LDS bank conflicts of the pipeline's access patterns (64 banks of 4 bytes, half a
+// wavefront per pass; and 32 banks, a quarter per pass); the line tiles' own padding (LS = Q + 1)
+// loses to these at every q.
+template <int Q, int NC>
+struct GaussJointCfg {
+  static constexpr int NT = (NC * Q * Q + 63) / 64 * 64;
+  // three wavefronts per SIMD where three workgroups' LDS fits a CU (q <= 8): the compiler then
+  // keeps to 168 registers (the Helmholtz variant, with more live values, keeps its default); q = 9
+  // fits two workgroups either way
+  static constexpr bool WPE3 = Q <= 8;
+  static constexpr int LS = (Q == 6) ? 6 : 9;
+  static constexpr int PL = (Q == 9) ? 83 : (Q == 8) ? 72 : (Q == 7) ? 71 : (Q == 6) ? 37 : Q * (Q + 1);
+  static constexpr int CS = (Q == 9) ? 747 : (Q == 8) ? 587 : (Q == 7) ? 523 : (Q == 6) ? 235 : Q * Q * (Q + 1);
+  static_assert(LS >= Q && PL >= (Q - 1) * LS + Q && CS >= (Q - 1) * PL + (Q - 1) * LS + Q, "disjoint buffers");
+};
+
+// Every component of one element per workgroup (vector problems, BP2 and BP4). Lane t works on
+// component c = t mod NC at line tile t / NC, with its own pair of LDS buffers; the pipeline is
+// gauss_element's, with workgroup barriers. Against a workgroup per component, this packs the
+// lanes densely, fits one and a half times the element-components per CU at the same register
+// budget, and reads the element's geometric factors once for all of its components: loaded whole
+// and coalesced at the start, so that their latency overlaps the node gather and the first pass,
+// and parked in LDS for the pointwise step (the NC lanes of a point read one address). The
+// component-minor order also makes the lanes of a node gather and store NC adjacent values.
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool HELM = false>
+__global__ void __launch_bounds__((GaussJointCfg<Q, NC>::NT)) __attribute__((amdgpu_waves_per_eu((GaussJointCfg<Q, NC>::WPE3 && !HELM) ? 3 : 1)))
+    k_gauss_joint(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
+                  const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin,
+                  const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
+  static_assert(P <= Q && NC > 1, "q >= p+1, several components");
+  static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
+  using L = GaussJointCfg<Q, NC>;
+  constexpr int NT = L::NT;
+  static_assert(NT > 64, "workgroup barriers between the steps");
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
+  __shared__ T S0[NC * L::CS];
+  __shared__ T S1[NC * L::CS];
+
+  const int t0 = threadIdx.x;
+  const bool lane_live = t0 < NC * Q2;
+  const int t = lane_live ? t0 : NC * Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
+  const int lt = t / NC;
+  const int c = t - lt * NC;
+  const int a = lt % Q, b = lt / Q;
+  const int64_t e = e_begin + blockIdx.x;
+  const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
+  const bool node_lane = lane_live && a < P && b < P;
+
+  constexpr int QN = (MODE == MODE_MASS ? 1 : 6) * Q2 * Q;  // the element's pointwise data
+  constexpr int QPL = (QN + NT - 1) / NT;
+  __shared__ TQ QS[QN];
+  TQ qv[QPL];
+  {
+    const TQ *const qsrc = qd + e * QN;
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+      const int o = i * NT + t0;
+      qv[i] = (o < QN) ? __builtin_nontemporal_load(qsrc + o) : TQ(0);
+    }
+  }
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+      const int o = i * NT + t0;
+      if (o < QN) QS[o] = qv[i];
+    }
+  };
+
+  int32_t nid[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+  const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
+
+  T old[P], z[P];
+  gauss_element<P, Q, MODE, NC, T, TQ, NT, false, HELM, true, decltype(stage), L::LS, L::PL>(
+      S0 + c * L::CS, S1 + c * L::CS, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y, old, z, qm, QS, stage);
   if (node_lane) {
 #pragma unroll
     for (int k = 0; k < P; ++k) y[(int64_t)nid[k] * NC + c] = old[k] + z[k];
