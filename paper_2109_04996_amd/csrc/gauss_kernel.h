@@ -144,13 +144,15 @@ __device__ __forceinline__ void elem_sync() {
 // QLDS: the caller has the element's pointwise data (qd's layout for one element) on its way to LDS at qs;
 // stage() writes it there and is called once, right after the first pass's LDS writes, so that the
 // loads overlap the node gather and the first interpolation; the pointwise step then reads qs, and
-// the old values of the scatter are requested two passes earlier.
+// the old values of the scatter are requested two passes early. EARLY_OLD: they are requested with
+// the node gather instead, their latency hidden behind the whole pipeline (for kernels whose
+// occupancy LDS bounds, which leaves the registers free).
 struct NoStage {
   __device__ void operator()() const {}
 };
 // LS, PL: LDS strides (doubles) of the r2 rows and r3 planes of a buffer, AT(i, j, k) = k PL + j LS + i.
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, int NT, bool ONEBUF = false, bool HELM = false,
-          bool QLDS = false, typename Stage = NoStage, int LS = Q + 1, int PL = Q *(Q + 1)>
+          bool QLDS = false, typename Stage = NoStage, int LS = Q + 1, int PL = Q *(Q + 1), bool EARLY_OLD = false>
 __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool lane_live,
                                               int64_t e, int c, const TQ *__restrict__ qd, const T *__restrict__ tab,
                                               const T *__restrict__ x, const int32_t (&nid)[P], uint32_t ob,
@@ -176,6 +178,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
       T u[P], uq[Q];
 #pragma unroll
       for (int k = 0; k < P; ++k) u[k] = x[(int64_t)nid[k] * NC + c];
+      if constexpr (QLDS && EARLY_OLD) load_old();
       interp_fwd<P, Q, T>(tI, u, uq);
       if (node_lane) {
 #pragma unroll
@@ -213,7 +216,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
         const TQ *const ql = qs + b * Q2 + a * Q;
 #pragma unroll
         for (int q = 0; q < Q; ++q) v[q] = ul[q] * static_cast<T>(ql[q]);
-        load_old();
+        if constexpr (!EARLY_OLD) load_old();
       } else {
         const TQ *const ql = qd + e * Q3 + b * Q2 + a * Q;
 #pragma unroll
@@ -353,7 +356,7 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 #pragma unroll
         for (int k = 0; k < Q; ++k) S0[AT(a, b, k)] = w[k];
       }
-      if constexpr (QLDS) load_old();
+      if constexpr (QLDS && !EARLY_OLD) load_old();
       elem_sync<NT>();
       // transposed interpolation along r1: thread (qj = a, qk = b), S0[i][qj][qk]
       {
@@ -450,6 +453,7 @@ struct GaussJointCfg {
   // keeps to 168 registers (the Helmholtz variant, with more live values, keeps its default); q = 9
   // fits two workgroups either way
   static constexpr bool WPE3 = Q <= 8;
+  // LDS-bound occupancy (q = 9, and the Helmholtz variant): the scatter's old values load early
   static constexpr int LS = (Q == 6) ? 6 : 9;
   static constexpr int PL = (Q == 9) ? 83 : (Q == 8) ? 72 : (Q == 7) ? 71 : (Q == 6) ? 37 : Q * (Q + 1);
   static constexpr int CS = (Q == 9) ? 747 : (Q == 8) ? 587 : (Q == 7) ? 523 : (Q == 6) ? 235 : Q * Q * (Q + 1);
@@ -514,7 +518,7 @@ __global__ void __launch_bounds__((GaussJointCfg<Q, NC>::NT)) __attribute__((amd
   const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
 
   T old[P], z[P];
-  gauss_element<P, Q, MODE, NC, T, TQ, NT, false, HELM, true, decltype(stage), L::LS, L::PL>(
+  gauss_element<P, Q, MODE, NC, T, TQ, NT, false, HELM, true, decltype(stage), L::LS, L::PL, !L::WPE3 || HELM>(
       S0 + c * L::CS, S1 + c * L::CS, a, b, lane_live, e, c, qd, tab, x, nid, ob, zero, y, old, z, qm, QS, stage);
   if (node_lane) {
 #pragma unroll
