@@ -72,8 +72,11 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // line-per-thread interpolating kernel, one element per workgroup: FP64 diffusion and FP64 mass
   // with q >= 7, where it beats the point-per-thread kernel; in FP32, and for mass at smaller q,
   // that kernel fills its wavefronts with several elements and wins
-  constexpr bool kGauss = std::is_same<T, double>::value && Q <= 9 && !EOUT &&
-                          ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+  constexpr bool kGaussQ = Q <= 9 && !EOUT && ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+  constexpr bool kGauss = std::is_same<T, double>::value && kGaussQ;
+  // several components in FP32: the joint-component kernel (all components of an element per
+  // workgroup) beats the point-per-thread kernel too
+  constexpr bool kJointF32 = std::is_same<T, float>::value && NC > 1 && kGaussQ;
   if constexpr (kGauss && gauss_strips(P, Q, MODE == MODE_MASS, NC)) {
     // on a mesh with strips: the strip scatter
     const hx_mesh_s &m = *op.mesh;
@@ -102,7 +105,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
       return HX_OK;
     }
   }
-  if constexpr (kGauss) {
+  if constexpr (kGauss || kJointF32) {
     const hx_mesh_s &m = *op.mesh;
     const T *zero = reinterpret_cast<const T *>(m.zeros.ptr);
     for (int c = 0; c < m.ncolors; ++c) {

@@ -51,6 +51,21 @@ def test_helmholtz_apply_matches_oracle(p, rule, q, ncomp):
             np.testing.assert_allclose(pr.diagonal().cpu().numpy(), fem.diagonal(H), rtol=1e-12)
 
 
+@pytest.mark.parametrize("p,q", [(7, 9), (5, 7)])
+def test_helmholtz_vector_fp32(p, q):
+    # three components in FP32 (the joint-component Gauss kernel): FP64 and FP32 geometric factors,
+    # against the oracle at the FP32 bound of the diffusion parity tests
+    N = 2 if p == 7 else 3
+    mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=3), p, 0.2, seed=p)
+    H = fem.assemble_helmholtz(mesh, p, q, "gauss", ALPHA, BETA)
+    with Problem(N, p, q, "gauss", "helmholtz", ncomp=3, mesh=mesh, helmholtz=(ALPHA, BETA)) as pr:
+        x = uniform_vector(mesh["nnodes"], 4, 3)
+        yr = fem.apply(H, x.astype(np.float32).astype(np.float64), 3)
+        for qprec in (hx.HX_FP64, hx.HX_FP32):
+            y32 = pr.apply_f32(pr.to_dev(x, torch.float32), qdata_prec=qprec).double().cpu().numpy()
+            assert rel(y32, yr) <= 6e-6, (qprec, rel(y32, yr))
+
+
 @pytest.mark.parametrize("p,rule,q,N", [(7, "gll", 8, 3), (7, "gauss", 8, 3), (6, "gauss", 8, 3),
                                         (4, "gll", 5, 3), (7, "gauss", 9, 2)])
 def test_helmholtz_lattice_paths(p, rule, q, N):
