@@ -37,6 +37,7 @@ CASES = (
     + [("diffusion", "gauss", p, p + 1, 1) for p in (2, 7)]
     + [("mass", "gauss", p, p + 1, 1) for p in (3, 8)]
     + [("mass", "gll", 3, 4, 1)]
+    + [("diffusion", "gauss", 8, 9, 1), ("mass", "gauss", 8, 9, 1)]
     + [("diffusion", "gll", p, p + 1, 3) for p in (2, 7)]
     + [("diffusion", "gauss", p, p + 2, 3) for p in (2, 4, 5, 6, 7, 8)]
     + [("diffusion", "gauss", 6, 7, 3)]
