@@ -5,7 +5,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 48] [--p 7] [--no-solve
 
 A step is one operator apply y = A x over the whole L-vector (all element colors), inputs resident in
 HBM. Prints one JSON line with the metric, the roofline object of the apply kernel (with the general
-index path beside it), the BP6 and Helmholtz apply lines, time-to-1e-8 solves on the same mesh and
+index path beside it), the BP6, Helmholtz and BP4 apply lines, time-to-1e-8 solves on the same mesh and
 across the other workloads (3-component p = 5..8, the variable-coefficient p = 6 problem, the learned
 preconditioner), and the oracle CPU baseline.
 """
@@ -676,10 +676,11 @@ def cpu_baseline(p: int, budget_s: float = 6.0):
 def extra_lines(out, mesh, N, p, roof):
     """Apply lines beside the headline on the same 48^3 lattice: the general index path (20% of the
     elements rotated, so the kernels read the full element restriction), BP6 (3-component collocated
-    diffusion) and the fused Helmholtz operator alpha A + beta B (collocated mass as a diagonal term)."""
+    diffusion) and the fused Helmholtz operator alpha A + beta B (collocated mass as a diagonal term);
+    and BP4 (3-component Gauss diffusion, q = p + 2) on a 40^3 lattice."""
     import torch
 
-    from paper_2109_04996_amd.inputs import rotate_elements
+    from paper_2109_04996_amd.inputs import lattice_mesh, rotate_elements
     from paper_2109_04996_amd.problem import Problem
     Q = p + 1
     E, n = mesh["nelem"], mesh["nnodes"]
@@ -704,6 +705,18 @@ def extra_lines(out, mesh, N, p, roof):
         out["helmholtz"] = dict(workload=f"fused alpha A + beta B (alpha = beta = 1), p={p}, q={Q} GLL-collocated "
                                          f"(mass diagonal), FP64, mesh A {N}^3, {n} DOFs", bound="hbm",
                                 peak=HBM_PEAK_GBS, **apply_line(ph, ab["total"], n))
+    torch.cuda.empty_cache()
+    # BP4 on its own 40^3 lattice (q = p + 2 Gauss points, 3 components: the joint-component kernel)
+    N4 = 40
+    print(f"[bench] BP4 vector apply ({N4}^3)", file=sys.stderr, flush=True)
+    mesh4 = lattice_mesh(N4, p, warp="A", shuffle_seed=0)
+    n4 = mesh4["nnodes"]
+    with Problem(N4, p, p + 2, "gauss", "diffusion", ncomp=3, mesh=mesh4) as p4:
+        ab = algorithmic_bytes(n4, mesh4["nelem"], p + 1, p + 2, 6, 3)
+        out["bp4"] = dict(workload=f"BP4 3-component diffusion apply, p={p}, q={p + 2} Gauss, FP64, mesh A {N4}^3, "
+                                   f"{n4} nodes x 3 interleaved", bound="hbm", peak=HBM_PEAK_GBS,
+                          **apply_line(p4, ab["total"], 3 * n4))
+    del mesh4
     torch.cuda.empty_cache()
 
 
