@@ -1,11 +1,12 @@
-// Fused apply with an interpolation step (Gauss points, BP1-BP4) for q <= 8, line per thread.
+// Fused apply with an interpolation step (Gauss points, BP1-BP4) for q <= 9, line per thread.
 //
 // Same operator as MODE_DIFF / MODE_MASS of apply_kernel.h (Benchmarks section: tensor-product
 // sum factorization; libCEED section: G^T B^T D B G in one pass), organised like the collocated
-// kernel (colloc_kernel.h): one wavefront per element, every 1D contraction on a whole line held
-// in one thread's registers, lines moving between the three directions through padded LDS
-// buffers, the 1D tables read with wave-uniform (scalar) loads, branch-free global loads and
-// the pointwise data streamed two planes ahead.
+// kernel (colloc_kernel.h): one or two wavefronts per element (k_gauss, k_gauss_strip), or all
+// components of an element in one workgroup (k_gauss_joint); every 1D contraction on a whole line
+// held in one thread's registers, lines moving between the three directions through padded LDS
+// buffers, the 1D tables read with wave-uniform (scalar) loads, branch-free global loads and the
+// pointwise data streamed two planes ahead (or staged in LDS).
 //
 // Diffusion, thread (a, b) of the Q x Q tile:
 //   interpolate x along r3 in registers (thread (i, j), P -> Q), then along r2 (thread (i, qk))
@@ -396,14 +397,15 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 #undef AT
 }
 
-// One element per workgroup. tab: interp [Q][P], D [Q][Q], then the even-odd coefficients of the
-// interpolation (EOInterp) and of D (EOLayout).
+// One element of a scalar operator per workgroup (several components: k_gauss_joint). tab: interp
+// [Q][P], D [Q][Q], then the even-odd coefficients of the interpolation (EOInterp) and of D (EOLayout).
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool HELM = false>
 __global__ void __launch_bounds__(GaussCfg<Q>::NT)
     k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
             const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
+  static_assert(NC == 1, "one component");
   static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
   constexpr int NT = GaussCfg<Q>::NT;
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
@@ -415,12 +417,8 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   const bool lane_live = lt0 < Q2;
   const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
   const int a = lt % Q, b = lt / Q;
-  // one component of one element per block (grid = (e_end - e_begin) NC); with several
-  // components, an XCD-aware order keeps an element's components on one XCD
-  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int64_t eo = item / NC;
-  const int c = item - (int)eo * NC;
-  const int64_t e = e_begin + eo;
+  const int64_t e = e_begin + blockIdx.x;  // grid = e_end - e_begin
+  constexpr int c = 0;
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
 
@@ -468,7 +466,9 @@ struct GaussJointCfg {
 // and coalesced at the start, so that their latency overlaps the node gather and the first pass,
 // and parked in LDS for the pointwise step (the NC lanes of a point read one address). The
 // component-minor order also makes the lanes of a node gather and store NC adjacent values.
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool HELM = false>
+// IDX: node ids as in k_colloc_strip (0 one per element node; 2 {base, s_j, s_k} per element, read
+// with scalar loads that the L2 serves, so the gather waits on no vector index load).
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__((GaussJointCfg<Q, NC>::NT)) __attribute__((amdgpu_waves_per_eu((GaussJointCfg<Q, NC>::WPE3 && !HELM) ? 3 : 1)))
     k_gauss_joint(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
                   const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin,
@@ -513,8 +513,16 @@ __global__ void __launch_bounds__((GaussJointCfg<Q, NC>::NT)) __attribute__((amd
   };
 
   int32_t nid[P];
+  if constexpr (IDX == 2) {
+    const int32_t *af = idx + e * 4;
+    const int32_t base = af[0] + an, sj = af[1], sk = af[2];
 #pragma unroll
-  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+    for (int k = 0; k < P; ++k) nid[k] = base + bn * sj + k * sk;
+  } else {
+    static_assert(IDX == 0, "full or affine node ids");
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+  }
   const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
 
   T old[P], z[P];
