@@ -120,10 +120,15 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
           hipLaunchKernelGGL((k_gauss_joint<P, Q, MODE, NC, T, TQ, 0, HELM>), dim3((unsigned)(e1 - e0)),
                              dim3(GaussJointCfg<Q, NC>::NT), 0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x),
                              static_cast<T *>(a.y), e0, zero, qm);
-      } else
-        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, HELM>), dim3((unsigned)(e1 - e0)), dim3(GaussCfg<Q>::NT), 0,
-                           s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1, zero,
-                           qm);
+      } else if (m.idx_affine.ptr) {
+        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 2, HELM>), dim3((unsigned)(e1 - e0)), dim3(GaussCfg<Q>::NT),
+                           0, s, m.idx_affine.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
+                           e0, e1, zero, qm);
+      } else {
+        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 0, HELM>), dim3((unsigned)(e1 - e0)), dim3(GaussCfg<Q>::NT),
+                           0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1,
+                           zero, qm);
+      }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_gauss launch");

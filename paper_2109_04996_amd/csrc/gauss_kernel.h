@@ -399,7 +399,8 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 
 // One element of a scalar operator per workgroup (several components: k_gauss_joint). tab: interp
 // [Q][P], D [Q][Q], then the even-odd coefficients of the interpolation (EOInterp) and of D (EOLayout).
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool HELM = false>
+// IDX: node ids as in k_gauss_joint (0 one per element node, 2 the element's affine numbering).
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(GaussCfg<Q>::NT)
     k_gauss(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
@@ -423,8 +424,16 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   const bool node_lane = lane_live && a < P && b < P;
 
   int32_t nid[P];
+  if constexpr (IDX == 2) {
+    const int32_t *af = idx + e * 4;
+    const int32_t base = af[0] + an, sj = af[1], sk = af[2];
 #pragma unroll
-  for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+    for (int k = 0; k < P; ++k) nid[k] = base + bn * sj + k * sk;
+  } else {
+    static_assert(IDX == 0, "full or affine node ids");
+#pragma unroll
+    for (int k = 0; k < P; ++k) nid[k] = __builtin_nontemporal_load(idx + e * P3 + k * P2 + bn * P + an);
+  }
   const uint32_t ob = node_lane ? (uint32_t)own[e * P2 + b * P + a] : 0xffffu;
 
   T old[P], z[P];
