@@ -77,7 +77,9 @@ __device__ __forceinline__ T ld_q(const TQ *p) {
     return static_cast<T>(__builtin_nontemporal_load(p));
 }
 
-template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT, bool HELM = false>
+// IDX: node ids, 0 one per element node, 2 the element's affine numbering {base, s_j, s_k} (16 bytes
+// per element instead of 4 P^3)
+template <int P, int Q, int MODE, int NC, typename T, typename TQ, bool EOUT, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_waves_per_eu(2)))
     k_apply(const int32_t *__restrict__ idx, const uint16_t *__restrict__ own, const TQ *__restrict__ qd,
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y,
@@ -110,8 +112,16 @@ __global__ void __launch_bounds__(EpbOf<Q>::v * Q * Q) __attribute__((amdgpu_wav
   int32_t nid[P];
   uint32_t ob = 0;
   if (node_thread) {
+    if constexpr (IDX == 2) {
+      const int32_t *af = idx + e * 4;
+      const int32_t base = af[0] + a + b * af[1], sk = af[2];
 #pragma unroll
-    for (int k = 0; k < P; ++k) nid[k] = idx[e * P3 + k * P2 + b * P + a];
+      for (int k = 0; k < P; ++k) nid[k] = base + k * sk;
+    } else {
+      static_assert(IDX == 0, "full or affine node ids");
+#pragma unroll
+      for (int k = 0; k < P; ++k) nid[k] = idx[e * P3 + k * P2 + b * P + a];
+    }
     ob = own[e * P2 + b * P + a];
   }
   const TQ *qe = qd + e * (int64_t)(NCQ * Q3) + b * Q + a;

@@ -141,8 +141,14 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     const int64_t e0 = EOUT ? 0 : m.color_start[c], e1 = EOUT ? m.nelem : m.color_start[c + 1];
     if (e1 <= e0) continue;
     const int64_t nb = (e1 - e0 + EPB - 1) / EPB * NC;  // blocks: element groups x components
-    hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT, HELM>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s, a.idx,
-                       a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1, qm);
+    if (m.idx_affine.ptr)
+      hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT, 2, HELM>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s,
+                         m.idx_affine.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order,
+                         e0, e1, qm);
+    else
+      hipLaunchKernelGGL((k_apply<P, Q, MODE, NC, T, TQ, EOUT, 0, HELM>), dim3((unsigned)nb), dim3(EPB * Q * Q), 0, s,
+                         a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), a.order, e0, e1,
+                         qm);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_apply launch");
