@@ -14,7 +14,7 @@
 // c_e = D_e^1/2 e_e - r~_e with e_e = A_ee^-1 r_e, z + D^-1 r is a restricted additive
 // Schwarz step over element blocks.
 //
-// Hot path: k_mlp_in (gather + scale + norm into bf16 rows), two bf16 matrix-core layers over all
+// Hot path: k_mlp_in (gather + scale + norm into bf16 rows, a wavefront per element), two bf16 matrix-core layers over all
 // elements (mlp.hip), k_mlp_gather_out (the node-wise sum over each node's element slots, with the
 // D^-1 r term of mode 1).
 #include <algorithm>
@@ -102,17 +102,18 @@ __global__ void k_wmult(int64_t n, const uint8_t *__restrict__ fm, float *__rest
 
 // network input of each element: r~_e / |r~_e| into the first half of its bf16 row (internal order; the
 // second half, the element's coefficient feature, is written once per operator by k_mlp_feat) and
-// |r~_e|. One pass over the element's nodes: each thread keeps its (at most kMaxIn) values in
-// registers while the block sums the squares (wavefront shuffles, then one LDS slot per wavefront).
+// |r~_e|. One wavefront per element: each lane keeps its (at most kMaxInW) values in registers while
+// the wavefront sums the squares with shuffles (no LDS, no barrier).
 // AFF: node ids from the element's affine numbering {base, s_j, s_k} (read with scalar loads) instead of
 // the full element restriction, so the gathers do not wait on an index load.
-constexpr int kMaxIn = (kMaxP * kMaxP * kMaxP + kThreads - 1) / kThreads;
+constexpr int kMaxInW = (kMaxP * kMaxP * kMaxP + 63) / 64;
 template <bool AFF>
 __global__ void __launch_bounds__(kThreads)
-    k_mlp_in(int P, const int32_t *__restrict__ idx, const double *__restrict__ r, const float *__restrict__ dis,
-             uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
-  __shared__ double sh[kThreads / 64];
-  const int64_t e = blockIdx.x;
+    k_mlp_in(int64_t E, int P, const int32_t *__restrict__ idx, const double *__restrict__ r,
+             const float *__restrict__ dis, uint16_t *__restrict__ X16, float *__restrict__ rnorm) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (e >= E) return;  // the whole wavefront
   const int P2 = P * P, P3 = P2 * P;
   int32_t base = 0, sj = 0, sk = 0;
   if constexpr (AFF) {
@@ -120,11 +121,11 @@ __global__ void __launch_bounds__(kThreads)
     sj = idx[e * 4 + 1];
     sk = idx[e * 4 + 2];
   }
-  double v[kMaxIn];
+  double v[kMaxInW];
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < kMaxIn; ++q) {
-    const int l = threadIdx.x + q * kThreads;
+  for (int q = 0; q < kMaxInW; ++q) {
+    const int l = lane + 64 * q;
     v[q] = 0.0;
     if (l < P3) {
       const int64_t nd = AFF ? (int64_t)base + l % P + (l / P) % P * sj + l / P2 * sk : idx[e * P3 + l];
@@ -134,20 +135,15 @@ __global__ void __launch_bounds__(kThreads)
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  double tot = 0.0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) tot += sh[w];
-  const double nrm = sqrt(tot);
+  const double nrm = sqrt(s);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   uint16_t *row = X16 + e * (int64_t)(2 * P3);
 #pragma unroll
-  for (int q = 0; q < kMaxIn; ++q) {
-    const int l = threadIdx.x + q * kThreads;
+  for (int q = 0; q < kMaxInW; ++q) {
+    const int l = lane + 64 * q;
     if (l < P3) row[l] = f32_to_bf16_bits((float)(v[q] * inv));
   }
-  if (threadIdx.x == 0) rnorm[e] = (float)nrm;
+  if (lane == 0) rnorm[e] = (float)nrm;
 }
 
 // the coefficient half of every element's network input row (constant for an operator)
@@ -295,11 +291,12 @@ hx_status mlp_precond_apply(hx_op_s &op, hx_mlp_s &net, int mode, const double *
     hipLaunchKernelGGL(k_mlp_feat, dim3(2048), dim3(256), 0, s, E, P3, op.mlp_feat16.ptr, op.mlp_x16.ptr);
     op.mlp_x16_feat = true;
   }
+  const dim3 gin((unsigned)((E + kThreads / 64 - 1) / (kThreads / 64)));
   if (m.idx_affine.ptr)
-    hipLaunchKernelGGL(k_mlp_in<true>, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx_affine.ptr, r,
-                       op.mlp_dis.ptr, op.mlp_x16.ptr, op.mlp_rnorm.ptr);
+    hipLaunchKernelGGL(k_mlp_in<true>, gin, dim3(kThreads), 0, s, E, op.P, m.idx_affine.ptr, r, op.mlp_dis.ptr,
+                       op.mlp_x16.ptr, op.mlp_rnorm.ptr);
   else
-    hipLaunchKernelGGL(k_mlp_in<false>, dim3((unsigned)E), dim3(kThreads), 0, s, op.P, m.idx.ptr, r, op.mlp_dis.ptr,
+    hipLaunchKernelGGL(k_mlp_in<false>, gin, dim3(kThreads), 0, s, E, op.P, m.idx.ptr, r, op.mlp_dis.ptr,
                        op.mlp_x16.ptr, op.mlp_rnorm.ptr);
   // the output rows come out scaled by |r~_e|
   if (hx_status st = mlp_layers_bf16(net, op.mlp_x16.ptr, E, op.mlp_h16.ptr, op.mlp_y.ptr, s, op.mlp_rnorm.ptr))
