@@ -250,6 +250,68 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// A layer with at most 16 NT outputs (the hidden layer): a workgroup takes 64 rows, 16 per
+// wavefront, and every output column, so each input row is read once; per chunk of KC = 32 U values
+// along K the weights of all columns are staged in LDS once for the four wavefronts (rows padded to
+// KC + 8 values: the 16 lanes of one row group read 16 distinct banks quadruples). Lane layout of
+// the products and the epilogue as in k_layer_bf16.
+template <typename TIN, bool TANH, typename TOUT, int NT, int U>
+__global__ void __launch_bounds__(256)
+    k_layer_wide(int64_t M, int N, int K, const TIN *__restrict__ In, const uint16_t *__restrict__ W,
+                 const float *__restrict__ bias, const float *__restrict__ row_scale, TOUT *__restrict__ Out) {
+  constexpr int KC = 32 * U, KP = KC + 8, SEGS = KC / 8;
+  __shared__ __align__(16) uint16_t Bs[NT * 16][KP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  const bool vec = (K & 7) == 0;
+  const int64_t row = m0 + r;
+  const bf16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  f32x4 acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int kb0 = 0; kb0 < K; kb0 += KC) {
+    // this wavefront's input values of the chunk, requested before the weights are staged
+    bf16x8 a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kb0 + 32 * u + kq, valid = K - k;
+      a[u] = (row < M && valid > 0) ? load8_bf16<TIN>(In + row * K + k, vec && valid >= 8, valid) : zero8;
+    }
+    __syncthreads();  // every wavefront is done with the previous chunk's weights
+    for (int t = threadIdx.x; t < NT * 16 * SEGS; t += 256) {
+      const int n = t / SEGS, k8 = (t - n * SEGS) * 8, k = kb0 + k8, valid = K - k;
+      const bf16x8 v = (n < N && valid > 0) ? load8_bf16<uint16_t>(W + (int64_t)n * K + k, vec && valid >= 8, valid)
+                                            : zero8;
+      *reinterpret_cast<bf16x8 *>(&Bs[n][k8]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[j * 16 + r][32 * u + kq]);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a[u]),
+                                                         __builtin_bit_cast(bf16x8_t, b), acc[j], 0, 0, 0);
+      }
+  }
+  const int rb = 4 * (lane >> 4);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int n = j * 16 + r;
+    if (n >= N) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t m = m0 + rb + t;
+      if (m >= M) continue;
+      float v = acc[j][t] + bias[n];
+      if (TANH) v = tanhf(v);
+      if (row_scale) v *= row_scale[m];
+      store_as(Out + m * N + n, v);
+    }
+  }
+}
+
 // launch one layer: NT = 2 column tiles and RT = 4 row tiles per wavefront up to 128 columns, else 4 and 2;
 // loads of U = 4 K steps in flight for K > 256, else 1; row_scale (optional) multiplies output row m
 template <typename TIN, bool TANH, typename TOUT>
@@ -279,7 +341,15 @@ void launch_layer(int64_t M, int N, int K, const TIN *In, const uint16_t *W, con
 hx_status mlp_layers_bf16(hx_mlp_s &net, const uint16_t *X16, int64_t batch, uint16_t *H16, float *Y, hipStream_t s,
                           const float *row_scale) {
   if (hx_status st = mlp_refresh_bf16(net, s)) return st;
-  launch_layer<uint16_t, true, uint16_t>(batch, net.n_hid, net.n_in, X16, net.W1b.ptr, net.p.ptr + net.off_b1, H16, s);
+  // the hidden layer: every column per workgroup, weights shared through LDS, where there are rows
+  // for more than about 1.25 workgroups per CU (below that, fewer rows per wavefront group win:
+  // 15.6k rows, p = 7, 0.167 against 0.176 ms per map; 24.4k, p = 6, 0.309 against 0.220)
+  if (net.n_hid <= 128 && batch >= 20000)
+    hipLaunchKernelGGL((k_layer_wide<uint16_t, true, uint16_t, 8, 4>), dim3((unsigned)((batch + 63) / 64)), dim3(256),
+                       0, s, batch, net.n_hid, net.n_in, X16, net.W1b.ptr, net.p.ptr + net.off_b1, nullptr, H16);
+  else
+    launch_layer<uint16_t, true, uint16_t>(batch, net.n_hid, net.n_in, X16, net.W1b.ptr, net.p.ptr + net.off_b1, H16,
+                                           s);
   launch_layer<uint16_t, false, float>(batch, net.n_out, net.n_hid, H16, net.W2b.ptr, net.p.ptr + net.off_b2, Y, s,
                                        row_scale);
   HX_HIP(hipGetLastError());
