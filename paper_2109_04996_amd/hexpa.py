@@ -149,6 +149,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2109_04996_amd.build` "
                           "(the operator has no CPU fallback)")
+    # PyTorch first: its HIP runtime must be the one in the process, or a library loaded ahead of it
+    # leaves torch seeing no GPU (the buffers and streams passed here are torch's)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, res, args in SIGNATURES:
         f = getattr(lib, name)
