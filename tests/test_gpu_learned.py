@@ -226,8 +226,8 @@ def _bf16(a):
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_learned_map_matches_oracle_composition(mode):
+@pytest.mark.parametrize("mode,p,N", [(0, 3, 4), (1, 3, 4), (1, 2, 28)])
+def test_learned_map_matches_oracle_composition(mode, p, N):
     # hx_op_mlp_precond against its definition composed on the CPU from the oracle: the assembled
     # diagonal D, kappa at the oracle's node coordinates, the FP64 network forward of the library's FP32
     # parameters, the 1/multiplicity weights of elem_nodes and the D^-1/2 scalings:
@@ -242,9 +242,11 @@ def test_learned_map_matches_oracle_composition(mode):
     #  (2) against the unrounded FP64 composition node by node within the first-order bound of those
     #      roundings: dZ = 2u |W1||x|, dH = (1 - H^2) dZ + u |H|, dY = |W2| dH + u |W2| (|H| + dH);
     #  (3) in norm within 2e-2 of the FP64 composition (the bf16 forward test's bound).
-    p, N, q = 3, 4, 5
+    # p = 2 on 28^3 elements: 21,952 network rows, where the hidden layer runs the kernel that stages its
+    # weights in LDS (20k rows and more), with 54 inputs per row (not a multiple of 8).
+    q = p + 2
     P3 = (p + 1) ** 3
-    print(f"\n[case] learned map mode={mode}", flush=True)
+    print(f"\n[case] learned map mode={mode} p={p} N={N}", flush=True)
     kp = kappa_field_params(1002, M=64)
     mesh = rotate_elements(lattice_mesh(N, p, warp="B", shuffle_seed=3), p, 0.15, seed=4)
     A = fem.assemble(mesh, p, q, "gauss", "diffusion", kappa=kp)
