@@ -23,7 +23,7 @@ constexpr int kStripP = 8; // the Gauss-point mass kernel uses strips at this ma
 // strips: p = 7 gains 9%, p = 6 1.5%, and three components lose 1.5%).
 constexpr bool colloc_strips(int P) { return (P >= 3 && P <= 5) || P == 8; }
 constexpr bool gauss_strips(int P, int Q, bool mass, int NC) {
-  return mass ? P == 8 : (NC == 1 && Q == 8 && (P == 7 || P == 8));
+  return mass ? (P == 8 && NC == 1) : (NC == 1 && Q == 8 && (P == 7 || P == 8));
 }
 constexpr bool strip_degree(int P) { return colloc_strips(P) || P == 7; }  // the mesh builds strips
 constexpr int kMinStripsPerColor = 512;  // collocated strips below P = 8: at least this many strip groups (workgroups) per color on average
