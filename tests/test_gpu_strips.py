@@ -1,9 +1,11 @@
-"""GPU tests of the strip scatter (collocated diffusion at every degree p >= 2, Gauss-point mass at p = 7).
+"""GPU tests of the strip scatter (collocated diffusion at every degree p >= 2, scalar Gauss-point mass at
+p = 7, scalar Gauss diffusion with q = 8 at p = 6, 7).
 
 The strip kernels scatter chains of face-adjacent elements together. Their results are checked
 against the FP64 oracle on meshes whose elements have random proper rotations (so chains break
 and strips of every length from 1 to 8 occur), and at the full benchmark size against the
-E-vector path (element kernel, no scatter) summed node by node.
+E-vector path (element kernel, no scatter) summed node by node. The 3-component Gauss cases of the
+same meshes run the joint-component kernel instead (element colors) and are checked the same way.
 """
 import numpy as np
 import pytest
