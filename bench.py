@@ -747,7 +747,7 @@ def main():
                     help="throughput per Jacobi-PCG iteration against problem size (BP5 and BP3 at p=7, 3e3 to 38M DOFs)")
     ap.add_argument("--pmc-kernels", action="store_true",
                     help="short run for the FLOP-rate counter pass: 4 applies of each hot kernel (BP5 p=7 FP64 and "
-                         "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms)")
+                         "FP32; p=6 q=8 Gauss FP64, FP32 and both bf16 matrix-core forms; BP4 p=7 q=9 FP64 and FP32)")
     ap.add_argument("--pmg-sweep", action="store_true",
                     help="p-multigrid FCG (FP64 and FP32 V-cycles) against Jacobi-PCG on BP5 p=7 over mesh sizes")
     ap.add_argument("--pmg-vcycles", type=int, default=0,
@@ -848,8 +848,20 @@ def main():
                 for _ in range(4):
                     p6.apply_bf16(x6f, y6f, prec=prec)
             torch.cuda.synchronize()
+        del mesh6
+        mesh4 = lattice_mesh(32, 7, warp="A", shuffle_seed=0)
+        with Problem(32, 7, 9, "gauss", "diffusion", ncomp=3, mesh=mesh4) as p4:
+            x4 = p4.to_dev(uniform_vector(mesh4["nnodes"], 1, 3))
+            y4 = p4.zeros()
+            x4f, y4f = x4.float(), p4.zeros(torch.float32)
+            for _ in range(4):
+                p4.apply(x4, y4)
+            for _ in range(4):
+                p4.apply_f32(x4f, hxm.HX_FP32, y4f)
+            torch.cuda.synchronize()
         print(json.dumps(dict(pmc_kernels=True, workloads=["bp5_p7_n48 FP64 and FP32",
-                                                           "p6_q8_gauss_n48 FP64, FP32, bf16, bf16 split"])),
+                                                           "p6_q8_gauss_n48 FP64, FP32, bf16, bf16 split",
+                                                           "bp4_p7_q9_n32 FP64 and FP32"])),
               flush=True)
         return
     if a.pmg_vcycles:
