@@ -72,11 +72,14 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
   // line-per-thread interpolating kernel, one element per workgroup: FP64 diffusion and FP64 mass
   // with q >= 7, where it beats the point-per-thread kernel; in FP32, and for mass at smaller q,
   // that kernel fills its wavefronts with several elements and wins
-  constexpr bool kGaussQ = Q <= 9 && !EOUT && ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
+  constexpr bool kGaussQ = Q <= 10 && !EOUT && ((MODE == MODE_DIFF && Q >= 6) || (MODE == MODE_MASS && Q >= 7));
   constexpr bool kGauss = std::is_same<T, double>::value && kGaussQ;
   // several components in FP32: the joint-component kernel (all components of an element per
   // workgroup) beats the point-per-thread kernel too
   constexpr bool kJointF32 = std::is_same<T, float>::value && NC > 1 && kGaussQ;
+  // several components in FP64: the joint kernel up to q = 9; at q = 10 its buffers and staged
+  // factors (99 KB of LDS) leave one workgroup per CU, and a workgroup per component runs instead
+  constexpr bool kJoint = NC > 1 && (kJointF32 || Q <= 9);
   if constexpr (kGauss && gauss_strips(P, Q, MODE == MODE_MASS, NC)) {
     // on a mesh with strips: the strip scatter
     const hx_mesh_s &m = *op.mesh;
@@ -111,7 +114,7 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
     for (int c = 0; c < m.ncolors; ++c) {
       const int64_t e0 = m.color_start[c], e1 = m.color_start[c + 1];
       if (e1 <= e0) continue;
-      if constexpr (NC > 1) {
+      if constexpr (kJoint) {
         if (m.idx_affine.ptr)
           hipLaunchKernelGGL((k_gauss_joint<P, Q, MODE, NC, T, TQ, 2, HELM>), dim3((unsigned)(e1 - e0)),
                              dim3(GaussJointCfg<Q, NC>::NT), 0, s, m.idx_affine.ptr, a.own, qd, tab,
@@ -121,13 +124,13 @@ hx_status launch_colors(const hx_op_s &op, const T *tab, const TQ *qd, const App
                              dim3(GaussJointCfg<Q, NC>::NT), 0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x),
                              static_cast<T *>(a.y), e0, zero, qm);
       } else if (m.idx_affine.ptr) {
-        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 2, HELM>), dim3((unsigned)(e1 - e0)), dim3(GaussCfg<Q>::NT),
-                           0, s, m.idx_affine.ptr, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                           e0, e1, zero, qm);
+        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 2, HELM>), dim3((unsigned)((e1 - e0) * NC)),
+                           dim3(GaussCfg<Q>::NT), 0, s, m.idx_affine.ptr, a.own, qd, tab, static_cast<const T *>(a.x),
+                           static_cast<T *>(a.y), e0, e1, zero, qm);
       } else {
-        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 0, HELM>), dim3((unsigned)(e1 - e0)), dim3(GaussCfg<Q>::NT),
-                           0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x), static_cast<T *>(a.y), e0, e1,
-                           zero, qm);
+        hipLaunchKernelGGL((k_gauss<P, Q, MODE, NC, T, TQ, 0, HELM>), dim3((unsigned)((e1 - e0) * NC)),
+                           dim3(GaussCfg<Q>::NT), 0, s, a.idx, a.own, qd, tab, static_cast<const T *>(a.x),
+                           static_cast<T *>(a.y), e0, e1, zero, qm);
       }
     }
     hipError_t e = hipGetLastError();

@@ -397,8 +397,9 @@ __device__ __forceinline__ void gauss_element(T *S0, T *S1, int a, int b, bool l
 #undef AT
 }
 
-// One element of a scalar operator per workgroup (several components: k_gauss_joint). tab: interp
-// [Q][P], D [Q][Q], then the even-odd coefficients of the interpolation (EOInterp) and of D (EOLayout).
+// One component of one element per workgroup (for several components k_gauss_joint is used up to
+// q = 9; at q = 10 its FP64 form needs too much LDS). tab: interp [Q][P], D [Q][Q], then the even-odd
+// coefficients of the interpolation (EOInterp) and of D (EOLayout).
 // IDX: node ids as in k_gauss_joint (0 one per element node, 2 the element's affine numbering).
 template <int P, int Q, int MODE, int NC, typename T, typename TQ, int IDX, bool HELM = false>
 __global__ void __launch_bounds__(GaussCfg<Q>::NT)
@@ -406,7 +407,6 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
             const T *__restrict__ tab, const T *__restrict__ x, T *__restrict__ y, int64_t e_begin, int64_t e_end,
             const T *__restrict__ zero, const TQ *__restrict__ qm = nullptr) {
   static_assert(Q * Q <= 128 && P <= Q, "at most two wavefronts per element, q >= p+1");
-  static_assert(NC == 1, "one component");
   static_assert(MODE == MODE_DIFF || MODE == MODE_MASS, "interpolating modes only");
   constexpr int NT = GaussCfg<Q>::NT;
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
@@ -418,8 +418,12 @@ __global__ void __launch_bounds__(GaussCfg<Q>::NT)
   const bool lane_live = lt0 < Q2;
   const int lt = lane_live ? lt0 : Q2 - 1;  // spare lanes shadow the last one (same values, no stores)
   const int a = lt % Q, b = lt / Q;
-  const int64_t e = e_begin + blockIdx.x;  // grid = e_end - e_begin
-  constexpr int c = 0;
+  // one component of one element per block (grid = (e_end - e_begin) NC); with several components an
+  // XCD-aware order keeps an element's components on one XCD
+  const int item = (NC > 1) ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int64_t eo = item / NC;
+  const int c = item - (int)eo * NC;
+  const int64_t e = e_begin + eo;
   const int an = a < P ? a : P - 1, bn = b < P ? b : P - 1;
   const bool node_lane = lane_live && a < P && b < P;
 
@@ -461,9 +465,10 @@ struct GaussJointCfg {
   // fits two workgroups either way
   static constexpr bool WPE3 = Q <= 8;
   // LDS-bound occupancy (q = 9, and the Helmholtz variant): the scatter's old values load early
-  static constexpr int LS = (Q == 6) ? 6 : 9;
-  static constexpr int PL = (Q == 9) ? 83 : (Q == 8) ? 72 : (Q == 7) ? 71 : (Q == 6) ? 37 : Q * (Q + 1);
-  static constexpr int CS = (Q == 9) ? 747 : (Q == 8) ? 587 : (Q == 7) ? 523 : (Q == 6) ? 235 : Q * Q * (Q + 1);
+  static constexpr int LS = (Q == 6) ? 6 : (Q == 10) ? 10 : 9;
+  static constexpr int PL = (Q == 10) ? 106 : (Q == 9) ? 83 : (Q == 8) ? 72 : (Q == 7) ? 71 : (Q == 6) ? 37 : Q * (Q + 1);
+  static constexpr int CS = (Q == 10) ? 1067 : (Q == 9) ? 747 : (Q == 8) ? 587 : (Q == 7) ? 523 : (Q == 6) ? 235
+                                                                                                : Q * Q * (Q + 1);
   static_assert(LS >= Q && PL >= (Q - 1) * LS + Q && CS >= (Q - 1) * PL + (Q - 1) * LS + Q, "disjoint buffers");
 };
 

@@ -41,7 +41,7 @@ CASES = (
     + [("diffusion", "gll", p, p + 1, 3) for p in (2, 7)]
     + [("diffusion", "gauss", p, p + 2, 3) for p in (2, 4, 5, 6, 7, 8)]
     + [("diffusion", "gauss", 6, 7, 3)]
-    + [("mass", "gauss", p, p + 2, 3) for p in (4, 5, 7)]
+    + [("mass", "gauss", p, p + 2, 3) for p in (4, 5, 7, 8)]
 )
 
 
@@ -94,7 +94,8 @@ def test_kappa_diffusion_matches_oracle():
 @pytest.mark.parametrize("kind,rule,p,q,ncomp", [("diffusion", "gll", 7, 8, 1), ("diffusion", "gauss", 6, 8, 1),
                                                  ("diffusion", "gauss", 5, 7, 3), ("mass", "gauss", 4, 6, 1),
                                                  ("diffusion", "gauss", 7, 9, 3), ("diffusion", "gauss", 4, 6, 3),
-                                                 ("mass", "gauss", 6, 8, 3)])
+                                                 ("mass", "gauss", 6, 8, 3), ("diffusion", "gauss", 8, 10, 3),
+                                                 ("mass", "gauss", 8, 10, 3)])
 @pytest.mark.parametrize("qprec", [hx.HX_FP64, hx.HX_FP32])
 def test_apply_fp32(kind, rule, p, q, ncomp, qprec):
     # FP32 arithmetic: each output is a sum of O(P) contractions of O(P) terms in 3 directions, done
