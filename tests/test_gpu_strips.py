@@ -5,7 +5,8 @@ The strip kernels scatter chains of face-adjacent elements together. Their resul
 against the FP64 oracle on meshes whose elements have random proper rotations (so chains break
 and strips of every length from 1 to 8 occur), and at the full benchmark size against the
 E-vector path (element kernel, no scatter) summed node by node. The 3-component Gauss cases of the
-same meshes run the joint-component kernel instead (element colors) and are checked the same way.
+same meshes run the joint-component kernel instead (element colors) and are checked the same way,
+on the oracle's meshes and at the 3-component benchmark size.
 """
 import numpy as np
 import pytest
@@ -39,7 +40,9 @@ def test_strip_counts(p, N, nstrips):
 
 @pytest.mark.parametrize("kind,rule,p,q", [("diffusion", "gll", 7, 8), ("mass", "gauss", 7, 9),
                                            ("diffusion", "gll", 4, 5), ("diffusion", "gll", 2, 3),
-                                           ("diffusion", "gauss", 6, 8), ("diffusion", "gauss", 7, 8)])
+                                           ("diffusion", "gauss", 6, 8), ("diffusion", "gauss", 7, 8),
+                                           ("diffusion", "gauss", 7, 9), ("diffusion", "gauss", 4, 6),
+                                           ("mass", "gauss", 6, 8)])
 @pytest.mark.parametrize("ncomp", [1, 3])
 def test_strip_apply_rotated_elements_matches_oracle(ncomp, kind, rule, p, q):
     N = 4 if p > 2 else 6
@@ -95,6 +98,43 @@ def test_strip_apply_matches_evector_sum(N, frac, kind, rule, p, q):
         assert err <= 1e-13, err
         # the strip path is deterministic
         assert torch.equal(y, pr.apply(x))
+
+
+def _scatter_evector_nc(pr, ye, nc):
+    """sum_e G_e^T y_e for nc interleaved components (y_e of shape (E, nc, nodes per element))."""
+    en = torch.from_numpy(pr.mesh["elem_nodes"].astype(np.int64)).cuda()
+    y = torch.zeros(pr.mesh["nnodes"] * nc, dtype=torch.float64, device="cuda")
+    for c in range(nc):
+        y.index_add_(0, (en * nc + c).view(-1), ye[:, c, :].contiguous().view(-1))
+    return y
+
+
+@pytest.mark.parametrize("kind,p,q,N,frac", [("diffusion", 7, 9, 9, 0.0), ("diffusion", 7, 9, 40, 0.0),
+                                             ("diffusion", 7, 9, 40, 0.2), ("mass", 7, 9, 9, 0.2),
+                                             ("diffusion", 6, 8, 9, 0.0), ("diffusion", 4, 6, 9, 0.2),
+                                             ("diffusion", 7, 8, 9, 0.0), ("mass", 6, 8, 9, 0.0)])
+def test_joint_kernel_matches_evector_sum(kind, p, q, N, frac):
+    # 3 components through the joint-component kernel on meshes with strips (which it does not use:
+    # element colors); N = 40 is the 3-component benchmark mesh, with and without rotated elements
+    print(f"\n[case] joint kernel vs E-vector N={N} frac={frac} {kind} p={p} q={q}", flush=True)
+    mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    if frac > 0:
+        mesh = rotate_elements(mesh, p, frac, seed=11)
+    with Problem(N, p, q, "gauss", kind, ncomp=3, mesh=mesh) as pr:
+        assert pr.stats["nstrips"] > 0
+        x = pr.to_dev(uniform_vector(mesh["nnodes"], 1, 3))
+        y = pr.apply(x)
+        ye = pr.apply_elem(x)
+        assert ye.shape == (mesh["nelem"], 3, (p + 1) ** 3)
+        yref = _scatter_evector_nc(pr, ye, 3)
+        err = float(torch.linalg.norm(y - yref) / torch.linalg.norm(yref))
+        assert err <= 1e-13, err
+        assert torch.equal(y, pr.apply(x))
+        # FP32 through the same strips
+        x32 = x.float()
+        y32 = pr.apply_f32(x32).double()
+        yref32 = _scatter_evector_nc(pr, pr.apply_elem(x32.double()), 3)
+        assert float(torch.linalg.norm(y32 - yref32) / torch.linalg.norm(yref32)) <= 6e-6
 
 
 @pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
