@@ -117,9 +117,11 @@ def read_heavy_probe(nbytes=4 << 30, parts=8):
     return (parts + 1) * m * 8 / (ms * 1e-3) / 1e9
 
 
-def apply_line(pr, ab, dofs, steps=50, warmup=5, x=None):
+def apply_line(pr, ab, dofs, steps=50, warmup=20, x=None):
     """Time ``steps`` applies of an operator (HIP events on the launch stream) and express the rate
-    against the algorithmic bytes ``ab`` (bytes per apply)."""
+    against the algorithmic bytes ``ab`` (bytes per apply). Each line follows seconds of host-side
+    mesh setup with the GPU idle; the first tens of milliseconds of applies after that run 5-10%
+    slower, hence 20 warm-up applies."""
     import torch
 
     from paper_2109_04996_amd.inputs import uniform_vector
