@@ -137,30 +137,36 @@ def test_joint_kernel_matches_evector_sum(kind, p, q, N, frac):
         assert float(torch.linalg.norm(y32 - yref32) / torch.linalg.norm(yref32)) <= 6e-6
 
 
-@pytest.mark.parametrize("kind,rule,q", [("diffusion", "gll", 8), ("mass", "gauss", 9)])
-def test_full_size_sampled_nodes_match_oracle(kind, rule, q):
-    """The benchmark workload (mesh A, 48^3 elements shuffled with seed 0, x ~ U[-1,1] from seed 1,
-    38.3M DOFs) through the strip launches the benchmark times, checked against the oracle at every
-    node of 16 seeded elements: interior, face, edge and corner nodes, strip ends among them. Each
-    reference value sums the oracle's dense element matrices of all elements holding the node."""
-    p, N = 7, 48
-    print(f"\n[case] full size N={N} p={p} q={q} {kind} sampled nodes", flush=True)
+@pytest.mark.parametrize("kind,rule,q,N,ncomp", [("diffusion", "gll", 8, 48, 1), ("mass", "gauss", 9, 48, 1),
+                                                  ("diffusion", "gauss", 9, 40, 3)])
+def test_full_size_sampled_nodes_match_oracle(kind, rule, q, N, ncomp):
+    """The benchmark workloads (mesh A, N^3 elements shuffled with seed 0, x ~ U[-1,1] from seed 1:
+    BP5 at 48^3, 38.3M DOFs; the 3-component BP4 line at 40^3, 3 x 22.2M DOFs) through the launches
+    the benchmark times, checked against the oracle at every node of 16 seeded elements: interior,
+    face, edge and corner nodes, strip ends among them. Each reference value sums the oracle's dense
+    element matrices of all elements holding the node (per component: the vector operators act on
+    each component alone)."""
+    p = 7
+    print(f"\n[case] full size N={N} p={p} q={q} {kind} ncomp={ncomp} sampled nodes", flush=True)
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
     en = mesh["elem_nodes"]
-    x = uniform_vector(mesh["nnodes"], 1)
-    with Problem(N, p, q, rule, kind, mesh=mesh) as pr:
-        assert pr.stats["nstrips"] == 13824 and pr.stats["nstrip_colors"] == 8
+    x = uniform_vector(mesh["nnodes"], 1, ncomp)
+    with Problem(N, p, q, rule, kind, ncomp=ncomp, mesh=mesh) as pr:
+        assert pr.stats["nstrips"] == N * N * (-(-N // 8)) and pr.stats["nstrip_colors"] == 8
         y = pr.apply(pr.to_dev(x)).cpu().numpy()
     rng = np.random.default_rng(5)
     sel = rng.choice(mesh["nelem"], 16, replace=False)
     targets = np.unique(en[sel].ravel())
     touch = np.flatnonzero(np.isin(en, targets).any(axis=1))
     Ae = fem.element_matrices(mesh, p, q, rule, kind, None, touch)
-    xe = x[en[touch].astype(np.int64)]
-    yref = np.zeros(mesh["nnodes"])
-    babs = np.zeros(mesh["nnodes"])
-    np.add.at(yref, en[touch].ravel(), np.einsum("eij,ej->ei", Ae, xe).ravel())
-    np.add.at(babs, en[touch].ravel(), np.einsum("eij,ej->ei", np.abs(Ae), np.abs(xe)).ravel())
-    err = rel(y[targets], yref[targets])
-    assert err <= 1e-12, err
-    assert np.max(np.abs(y[targets] - yref[targets])) <= 1e-12 * babs[targets].max()
+    xv = x.reshape(mesh["nnodes"], ncomp)
+    yv = y.reshape(mesh["nnodes"], ncomp)
+    for c in range(ncomp):
+        xe = xv[en[touch].astype(np.int64), c]
+        yref = np.zeros(mesh["nnodes"])
+        babs = np.zeros(mesh["nnodes"])
+        np.add.at(yref, en[touch].ravel(), np.einsum("eij,ej->ei", Ae, xe).ravel())
+        np.add.at(babs, en[touch].ravel(), np.einsum("eij,ej->ei", np.abs(Ae), np.abs(xe)).ravel())
+        err = rel(yv[targets, c], yref[targets])
+        assert err <= 1e-12, (c, err)
+        assert np.max(np.abs(yv[targets, c] - yref[targets])) <= 1e-12 * babs[targets].max()
