@@ -137,22 +137,30 @@ def test_joint_kernel_matches_evector_sum(kind, p, q, N, frac):
         assert float(torch.linalg.norm(y32 - yref32) / torch.linalg.norm(yref32)) <= 6e-6
 
 
-@pytest.mark.parametrize("kind,rule,q,N,ncomp", [("diffusion", "gll", 8, 48, 1), ("mass", "gauss", 9, 48, 1),
-                                                  ("diffusion", "gauss", 9, 40, 3)])
-def test_full_size_sampled_nodes_match_oracle(kind, rule, q, N, ncomp):
+@pytest.mark.parametrize("kind,rule,q,N,ncomp,rot", [("diffusion", "gll", 8, 48, 1, 0.0), ("mass", "gauss", 9, 48, 1, 0.0),
+                                                      ("diffusion", "gauss", 9, 40, 3, 0.0),
+                                                      ("diffusion", "gll", 8, 48, 3, 0.0),
+                                                      ("diffusion", "gll", 8, 48, 1, 0.2)])
+def test_full_size_sampled_nodes_match_oracle(kind, rule, q, N, ncomp, rot):
     """The benchmark workloads (mesh A, N^3 elements shuffled with seed 0, x ~ U[-1,1] from seed 1:
-    BP5 at 48^3, 38.3M DOFs; the 3-component BP4 line at 40^3, 3 x 22.2M DOFs) through the launches
+    BP5 at 48^3, 38.3M DOFs; the 3-component BP4 line at 40^3, 3 x 22.2M DOFs; BP6 at 48^3; BP5 on
+    the same mesh with 20% of its elements rotated, seed 5, the full-index path) through the launches
     the benchmark times, checked against the oracle at every node of 16 seeded elements: interior,
     face, edge and corner nodes, strip ends among them. Each reference value sums the oracle's dense
     element matrices of all elements holding the node (per component: the vector operators act on
     each component alone)."""
     p = 7
-    print(f"\n[case] full size N={N} p={p} q={q} {kind} ncomp={ncomp} sampled nodes", flush=True)
+    print(f"\n[case] full size N={N} p={p} q={q} {kind} ncomp={ncomp} rotated {rot} sampled nodes", flush=True)
     mesh = lattice_mesh(N, p, warp="A", shuffle_seed=0)
+    if rot > 0:
+        mesh = rotate_elements(mesh, p, rot, seed=5)
     en = mesh["elem_nodes"]
     x = uniform_vector(mesh["nnodes"], 1, ncomp)
     with Problem(N, p, q, rule, kind, ncomp=ncomp, mesh=mesh) as pr:
-        assert pr.stats["nstrips"] == N * N * (-(-N // 8)) and pr.stats["nstrip_colors"] == 8
+        if rot > 0:
+            assert pr.stats["index_mode"] == 0 and pr.stats["nstrips"] > 0
+        else:
+            assert pr.stats["nstrips"] == N * N * (-(-N // 8)) and pr.stats["nstrip_colors"] == 8
         y = pr.apply(pr.to_dev(x)).cpu().numpy()
     rng = np.random.default_rng(5)
     sel = rng.choice(mesh["nelem"], 16, replace=False)
