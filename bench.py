@@ -742,7 +742,7 @@ def main():
                     help="apply throughput over the size sweep and the other operator kinds (one JSON line each)")
     ap.add_argument("--pmc-workload", default="bp5", choices=["bp5", "general", "bp4"],
                     help="workload of --pmc-run: BP5 p=7 48^3 (default), the same with 20%% of the elements rotated, "
-                         "or BP4 3-component p=7 q=9 32^3")
+                         "or BP4 3-component p=7 q=9 40^3")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB reference copy, then 6 applies")
     ap.add_argument("--cg-sweep", action="store_true",
@@ -803,8 +803,9 @@ def main():
             mesh_w = rotate_elements(lattice_mesh(48, 7, warp="A", shuffle_seed=0), 7, 0.2, seed=5)
             pw = Problem(48, 7, 8, "gll", "diffusion", mesh=mesh_w)
         else:
-            mesh_w = lattice_mesh(32, 7, warp="A", shuffle_seed=0)
-            pw = Problem(32, 7, 9, "gauss", "diffusion", ncomp=3, mesh=mesh_w)
+            # the BP4 line's size (40^3 elements, 3 x 22.2M DOFs)
+            mesh_w = lattice_mesh(40, 7, warp="A", shuffle_seed=0)
+            pw = Problem(40, 7, 9, "gauss", "diffusion", ncomp=3, mesh=mesh_w)
         xw = pw.to_dev(uniform_vector(mesh_w["nnodes"], 1, pw.ncomp))
         yw = pw.zeros()
         ref_a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
