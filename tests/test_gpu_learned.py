@@ -155,10 +155,14 @@ def test_learned_fcg_solve_and_gain(trained):
         print("\n[learned] gain record:", res, flush=True)
         for name, r in res.items():
             assert r["true_rel_residual"] <= 1.05e-8, (name, r)
-        # the learned preconditioner, with or without its fallback, must finish within the
-        # fallback's own budget plus the stall window
+        # The learned map either carries the whole solve or its stall check hands the iterate to
+        # Jacobi-PCG within the stall window (20 iterations, checked every 10): either way the solve
+        # takes at most Jacobi-PCG's own iterations plus 40, the fallback's among them. What the trained
+        # network gains per application is asserted by test_learned_map_gain_per_application.
         lr = res["learned"]
-        assert lr["iterations"] <= res["jacobi"]["iterations"] + 40 or lr["fallback_used"] == 1
+        assert lr["iterations"] <= res["jacobi"]["iterations"] + 40, (lr, res["jacobi"])
+        if lr["fallback_used"]:
+            assert lr["fallback_iterations"] <= lr["iterations"], lr
 
 
 def _anorm_reduction(pr, e, z, r):
