@@ -462,7 +462,14 @@ def suite_learned(p=5, N_eval=35, N_train=12, train_seeds=(1000, 1001, 1002, 100
     best_learned = min(t["learned"], t["learned_cheb4"], t["pmg_learned_smoother"])
     best_plain = min(t["jacobi"], t["chebyshev4"], t["chebyshev4_fp32"], t["pmg"])
     saved = best_plain - best_learned
-    out["break_even_solves"] = (round((t_data + info["seconds"]) / saved, 1) if saved > 0 else None)
+    cost = t_data + info["seconds"]  # training data and training, paid once per operator family
+    out["break_even_solves"] = (round(cost / saved, 1) if saved > 0 else None)
+    saved_j = t["jacobi"] - best_learned
+    out["break_even_solves_vs_jacobi"] = (round(cost / saved_j, 1) if saved_j > 0 else None)
+    out["break_even_note"] = ("solves after which the training cost is repaid by the time the fastest learned form "
+                              "saves per solve: over the fastest form without the network (break_even_solves), "
+                              "and over plain FP64 Jacobi-PCG (break_even_solves_vs_jacobi); null where the learned "
+                              "form saves nothing")
     pr.close()
     hx.hx_mlp_destroy(net)
     return out
