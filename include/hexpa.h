@@ -146,6 +146,32 @@ hx_status hx_mesh_get_order(hx_mesh mesh, int32_t *order, int64_t *color_start);
 
 void hx_mesh_destroy(hx_mesh mesh);
 
+/* Host-only mesh plan: the element coloring, internal order, ownership masks,
+ * index mode and strips that hx_mesh_create computes (libCEED section: the
+ * element restriction G and the atomic-free form of its transpose), built on
+ * the host with no HIP call and no device memory, so that the host logic can
+ * be inspected where there is no GPU. Arguments and errors as hx_mesh_create
+ * (no HX_EHIP). hx_mesh_get_stats, hx_mesh_get_order, hx_mesh_plan_arrays and
+ * hx_mesh_destroy accept the result; operator creation rejects it (HX_EINVAL). */
+hx_status hx_mesh_plan(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
+                       const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out);
+
+/* Copy a plan's arrays to host buffers the caller owns (any may be NULL),
+ * P = p+1, all in internal element order (hx_mesh_get_order):
+ *   idx               nelem*P^3 int32, node ids, local order i + P(j + Pk)
+ *   own               nelem*P^2 uint16, [t][j*P+i] bit k: element t is the first
+ *                     element (internal order) listing node (i,j,k)
+ *   strip_elems       nstrip_groups*8 int32: the internal positions of each
+ *                     strip group's elements, -1 past its last
+ *   strip_link        nstrip_groups uint8: bit w, slot w+1 continues slot w's strip
+ *   strip_own         nelem*P^2 uint16, ownership in strip order (element w > 0
+ *                     of a strip never owns its i = 0 face)
+ *   strip_color_start nstrip_colors+1 int64, in groups
+ * The strip arrays are empty (nothing copied) when nstrips == 0.
+ * Errors: HX_EINVAL (null mesh, or a mesh from hx_mesh_create). */
+hx_status hx_mesh_plan_arrays(hx_mesh mesh, int32_t *idx, uint16_t *own, int32_t *strip_elems,
+                              uint8_t *strip_link, uint16_t *strip_own, int64_t *strip_color_start);
+
 /* ------------------------------------------------------------------------ */
 /* Bases                                                                     */
 /* ------------------------------------------------------------------------ */

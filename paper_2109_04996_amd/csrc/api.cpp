@@ -92,6 +92,7 @@ hx_status op_create(hx_mesh mesh, hx_basis basis, int kind, int ncomp, double al
   if (!out) return fail(HX_EINVAL, "out is null");
   *out = nullptr;
   if (!mesh || !basis) return fail(HX_EINVAL, "null mesh or basis");
+  if (mesh->host_only) return fail(HX_EINVAL, "the mesh is a host-only plan (hx_mesh_plan): create it with hx_mesh_create");
   if (ncomp != 1 && ncomp != 3) return fail(HX_EINVAL, "ncomp must be 1 or 3");
   if (basis->b.p != mesh->p) return fail(HX_EUNSUPPORTED, "basis degree differs from the mesh degree");
   if (kappa && kind == HX_MASS) return fail(HX_EINVAL, "a coefficient applies to HX_DIFFUSION only");

@@ -122,6 +122,13 @@ struct hx_mesh_s {
   hx::DevBuf<int32_t> gather_ptr, gather_slot;
   // the same in internal element order: slots e * P^3 + l (internal position e), ascending (made on first use)
   hx::DevBuf<int32_t> slot_ptr, slot_idx;
+  int index_mode = 0;  // 0 full index array, 1 one id per r1-row, 2 affine numbering
+  // A host-only plan (hx_mesh_plan) holds no device memory: the arrays the device buffers would hold stay
+  // on the host for inspection, and operators reject the mesh.
+  bool host_only = false;
+  std::vector<int32_t> h_idx, h_strip_elems;
+  std::vector<uint16_t> h_own, h_strip_own;
+  std::vector<uint8_t> h_strip_link;
 };
 
 struct hx_op_s {

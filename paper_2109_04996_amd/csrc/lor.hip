@@ -280,6 +280,7 @@ extern "C" hx_status hx_op_create_lor(hx_mesh mesh, const hx_kappa_rff *kappa, h
   if (!out) return fail(HX_EINVAL, "out is null");
   *out = nullptr;
   if (!mesh) return fail(HX_EINVAL, "null mesh");
+  if (mesh->host_only) return fail(HX_EINVAL, "the mesh is a host-only plan (hx_mesh_plan): create it with hx_mesh_create");
   if (kappa && (kappa->M < 0 || (kappa->M > 0 && (!kappa->omega || !kappa->phase))))
     return fail(HX_EINVAL, "kappa: M >= 0 and omega/phase non-null");
   int dev = 0;

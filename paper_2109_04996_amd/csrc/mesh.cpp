@@ -325,8 +325,12 @@ extern "C" hx_status hx_mesh_nodes_trilinear(int p, int64_t nelem, const int64_t
   return HX_OK;
 }
 
-extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
-                                    const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out) {
+namespace {
+
+// The mesh builder behind hx_mesh_create (device = true: the arrays go to the current device) and
+// hx_mesh_plan (device = false: they stay on the host, and no HIP call is made).
+hx_status mesh_build(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes, const double *node_xyz,
+                     const uint8_t *dirichlet, bool device, hx_mesh *out) {
   if (!out) return hx::fail(HX_EINVAL, "out is null");
   *out = nullptr;
   if (p < 1 || p > hx::kMaxP - 1) return hx::fail(HX_EINVAL, "p must be in 1..8");
@@ -345,7 +349,7 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
   m->P = P;
   m->nelem = nelem;
   m->nnodes = nnodes;
-  (void)hipGetDevice(&m->device);
+  if (device) (void)hipGetDevice(&m->device);
   m->h_xyz.assign(node_xyz, node_xyz + nnodes * 3);
 
   // coloring: greedy in two visiting orders (Morton of centroids; centroid z-y-x rows),
@@ -450,7 +454,8 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
         rb[(size_t)t * P2 + r] = row[0];
       }
     if (rows) {
-      hipError_t e = m->idx_rows.upload(rb.data(), rb.size());
+      m->index_mode = 1;
+      hipError_t e = device ? m->idx_rows.upload(rb.data(), rb.size()) : hipSuccess;
       if (e != hipSuccess) {
         delete m;
         return hx::hip_fail(e, "mesh upload");
@@ -475,7 +480,8 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       }
       if (!affine) af.clear();
       if (affine) {
-        e = m->idx_affine.upload(af.data(), af.size());
+        m->index_mode = 2;
+        e = device ? m->idx_affine.upload(af.data(), af.size()) : hipSuccess;
         if (e != hipSuccess) {
           delete m;
           return hx::hip_fail(e, "mesh upload");
@@ -514,6 +520,18 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
       m->nfree += fm[n];
     }
   }
+  if (!device) {
+    m->host_only = true;
+    m->h_idx = std::move(idx);
+    m->h_own = std::move(own);
+    if (strips) {
+      m->h_strip_elems = std::move(selems);
+      m->h_strip_link = std::move(glink);
+      m->h_strip_own = std::move(sown);
+    }
+    *out = m;
+    return HX_OK;
+  }
   hipError_t e;
   if ((e = m->idx.upload(idx.data(), idx.size())) != hipSuccess ||
       (e = m->own.upload(own.data(), own.size())) != hipSuccess ||
@@ -528,6 +546,31 @@ extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const 
     return hx::hip_fail(e, "mesh upload");
   }
   *out = m;
+  return HX_OK;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_mesh_create(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
+                                    const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out) {
+  return mesh_build(p, nelem, nnodes, elem_nodes, node_xyz, dirichlet, true, out);
+}
+
+extern "C" hx_status hx_mesh_plan(int p, int64_t nelem, int64_t nnodes, const int32_t *elem_nodes,
+                                  const double *node_xyz, const uint8_t *dirichlet, hx_mesh *out) {
+  return mesh_build(p, nelem, nnodes, elem_nodes, node_xyz, dirichlet, false, out);
+}
+
+extern "C" hx_status hx_mesh_plan_arrays(hx_mesh m, int32_t *idx, uint16_t *own, int32_t *strip_elems,
+                                         uint8_t *strip_link, uint16_t *strip_own, int64_t *strip_color_start) {
+  if (!m) return hx::fail(HX_EINVAL, "null mesh");
+  if (!m->host_only) return hx::fail(HX_EINVAL, "the mesh is not a host-only plan (hx_mesh_plan)");
+  if (idx) std::copy(m->h_idx.begin(), m->h_idx.end(), idx);
+  if (own) std::copy(m->h_own.begin(), m->h_own.end(), own);
+  if (strip_elems) std::copy(m->h_strip_elems.begin(), m->h_strip_elems.end(), strip_elems);
+  if (strip_link) std::copy(m->h_strip_link.begin(), m->h_strip_link.end(), strip_link);
+  if (strip_own) std::copy(m->h_strip_own.begin(), m->h_strip_own.end(), strip_own);
+  if (strip_color_start) std::copy(m->strip_color_start.begin(), m->strip_color_start.end(), strip_color_start);
   return HX_OK;
 }
 
@@ -590,7 +633,7 @@ extern "C" hx_status hx_mesh_get_stats(hx_mesh m, hx_mesh_stats *s) {
   s->nstrips = m->nstrips;
   s->nstrip_colors = m->nstrip_colors;
   s->nstrip_groups = m->nstrip_groups;
-  s->index_mode = m->idx_affine.ptr ? 2 : m->idx_rows.ptr ? 1 : 0;
+  s->index_mode = m->index_mode;
   return HX_OK;
 }
 

@@ -95,6 +95,8 @@ SIGNATURES = [
     ("hx_mesh_create", C.c_int, [C.c_int, _I64, _I64, _VP, _VP, _VP, C.POINTER(_VP)]),
     ("hx_mesh_get_stats", C.c_int, [_VP, C.POINTER(hx_mesh_stats)]),
     ("hx_mesh_get_order", C.c_int, [_VP, _VP, _VP]),
+    ("hx_mesh_plan", C.c_int, [C.c_int, _I64, _I64, _VP, _VP, _VP, C.POINTER(_VP)]),
+    ("hx_mesh_plan_arrays", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("hx_mesh_destroy", None, [_VP]),
     ("hx_basis_create", C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(_VP)]),
     ("hx_basis_get_tables", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
@@ -214,6 +216,33 @@ def hx_mesh_create(p, elem_nodes: np.ndarray, node_xyz: np.ndarray, dirichlet: n
     _check(load().hx_mesh_create(p, en.shape[0], xyz.shape[0], _ptr(en), _ptr(xyz), _ptr(d), C.byref(h)),
            "hx_mesh_create")
     return h
+
+
+def hx_mesh_plan(p, elem_nodes: np.ndarray, node_xyz: np.ndarray, dirichlet: np.ndarray | None):
+    en = np.ascontiguousarray(elem_nodes, dtype=np.int32)
+    xyz = np.ascontiguousarray(node_xyz, dtype=np.float64)
+    d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    h = C.c_void_p()
+    _check(load().hx_mesh_plan(p, en.shape[0], xyz.shape[0], _ptr(en), _ptr(xyz), _ptr(d), C.byref(h)),
+           "hx_mesh_plan")
+    return h
+
+
+def hx_mesh_plan_arrays(plan, p: int) -> dict:
+    st = hx_mesh_get_stats(plan)
+    P = p + 1
+    E, G = st["nelem"], st["nstrip_groups"]
+    out = dict(idx=np.zeros((E, P ** 3), np.int32), own=np.zeros((E, P * P), np.uint16),
+               strip_elems=np.zeros((G, 8), np.int32), strip_link=np.zeros(G, np.uint8),
+               strip_own=np.zeros((E, P * P), np.uint16),
+               strip_color_start=np.zeros(st["nstrip_colors"] + 1, np.int64))
+    strips = st["nstrips"] > 0
+    _check(load().hx_mesh_plan_arrays(plan, _ptr(out["idx"]), _ptr(out["own"]),
+                                      _ptr(out["strip_elems"]) if strips else None,
+                                      _ptr(out["strip_link"]) if strips else None,
+                                      _ptr(out["strip_own"]) if strips else None,
+                                      _ptr(out["strip_color_start"]) if strips else None), "hx_mesh_plan_arrays")
+    return out
 
 
 def hx_mesh_get_stats(mesh) -> dict:
