@@ -191,3 +191,17 @@ def test_plan_rejects_bad_input():
     twice[0, 1] = twice[0, 0]  # an element listing one node twice
     with pytest.raises(hx.HexpaError):
         hx.hx_mesh_plan(2, twice, xyz, None)
+
+
+def test_benchmark_mesh_plan():
+    # the BP5 p = 7 benchmark mesh (mesh A, 48^3 elements shuffled with seed 0, 38,272,753 nodes): 8
+    # launches of 1,728 strips of 8 elements, the affine numbering, 8 element colors of 13,824, and
+    # one owner per node under both orders (bit counts; the positions are checked on the small meshes)
+    st, _, cs, arr = _plan(lattice_mesh(48, 7, warp="A", shuffle_seed=0), 7)
+    assert (st["nstrips"], st["nstrip_colors"], st["nstrip_groups"], st["index_mode"]) == (13824, 8, 13824, 2)
+    assert np.array_equal(np.diff(arr["strip_color_start"]), np.full(8, 1728))
+    assert np.all(arr["strip_link"] == 0x7f) and np.all(arr["strip_elems"] >= 0)
+    assert st["ncolors"] == 8 and np.array_equal(np.diff(cs), np.full(8, 13824))
+    assert _launches_disjoint(arr["idx"], cs)
+    for own in (arr["own"], arr["strip_own"]):
+        assert int(np.unpackbits(own.view(np.uint8)).sum()) == st["nnodes"] == 38272753
