@@ -157,6 +157,12 @@ def test_checks_catch_a_wrong_coloring():
     st, order, cs, arr = _plan(mesh, 3)
     merged = np.array([cs[0], cs[2]] + list(cs[3:]))  # two colors launched together
     assert _launches_disjoint(arr["idx"], cs) and not _launches_disjoint(arr["idx"], merged)
+    strips = _strips(arr, st) if st["nstrips"] else []
+    assert strips, "the 4^3 lattice at p = 3 has strips"
+    c0 = [sorted(set(arr["idx"][s].ravel())) for c, s in strips if c == 0]
+    c1 = [sorted(set(arr["idx"][s].ravel())) for c, s in strips if c == 1]
+    joined = np.concatenate(c0 + c1)  # two strip colors launched together share nodes
+    assert np.unique(joined).size < joined.size
     own = arr["own"].copy()
     own[0, 0] ^= 1  # drop (or add) one owner bit
     pos = np.stack(np.meshgrid(np.arange(st["nelem"]), np.arange(64), indexing="ij"), axis=-1).reshape(-1, 2)
