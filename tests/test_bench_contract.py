@@ -30,3 +30,17 @@ def test_bp5_bytes_per_dof():
     # three interleaved components: vectors triple, the factors and ids do not
     ab3 = bench.algorithmic_bytes(n, E, p + 1, p + 1, ncomp=3)
     assert ab3["total"] - ab["total"] == 2 * ab["xy"]
+
+
+def test_secondary_line_bytes_per_dof():
+    # the bench line's other apply records, from the element and node counts alone
+    # BP4: p = 7, q = 9 Gauss, 40^3 elements, 3 components; 9^3 points of 6 factors per element
+    n4, E4 = (7 * 40 + 1) ** 3, 40 ** 3
+    ab = bench.algorithmic_bytes(n4, E4, 8, 9, 6, 3)
+    assert ab["total"] == 48 * n4 + 8 * 6 * 729 * E4 + 4 * 512 * E4 == 3_435_585_968
+    assert round(ab["total"] / (3 * n4), 2) == 51.61
+    # BP6: p = 7 collocated, 48^3 elements, 3 components
+    n6, E6 = (7 * 48 + 1) ** 3, 48 ** 3
+    assert round(bench.algorithmic_bytes(n6, E6, 8, 8, 6, 3)["total"] / (3 * n6), 2) == 41.64
+    # fused Helmholtz alpha A + beta B: a seventh stored value per point (beta w detJ)
+    assert round(bench.algorithmic_bytes(n6, E6, 8, 8, 7, 1)["total"] / n6, 2) == 104.77
