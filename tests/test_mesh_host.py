@@ -82,6 +82,11 @@ CASES = [
     ("20% rotated N=8 p=7", lambda: rotate_elements(lattice_mesh(8, 7, warp="A", shuffle_seed=0), 7, 0.2, 5), 7, 0),
     ("15% rotated N=6 p=3 warp B", lambda: rotate_elements(lattice_mesh(6, 3, warp="B", shuffle_seed=0), 3, 0.15, 7), 3, 0),
     ("one element p=5", lambda: lattice_mesh(1, 5, warp="A", shuffle_seed=0), 5, 2),
+] + [
+    (f"lattice N=4 p={q}", (lambda q=q: lattice_mesh(4, q, warp="A", shuffle_seed=q)), q, 2) for q in (1, 3, 5, 6, 8)
+] + [
+    (f"25% rotated N=4 p={q} warp B", (lambda q=q: rotate_elements(lattice_mesh(4, q, warp="B", shuffle_seed=q), q,
+                                                                    0.25, q)), q, 0) for q in (1, 2, 4, 7, 8)
 ]
 
 
